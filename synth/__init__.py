@@ -1,0 +1,120 @@
+"""Seeded synthetic inputs for the random-projection workloads.
+
+This module is shared by the library's tests and benchmark and by the CPU
+oracle.  It draws inputs only (matrices with a prescribed spectrum, Tucker
+tensors, problem lists); it contains none of the projection method's own
+arithmetic (no Omega generation, no split, no projection, no QR/SVD of the
+method).  Two back ends draw the same *distributions*:
+
+* NumPy (``np_*``): small and medium inputs, deterministic from the seed on any
+  host.
+* torch (``torch_*``): the full-size inputs (up to 4 GiB of FP32), drawn on the
+  GPU; deterministic from the seed on a given torch build.  The oracle gets the
+  very same array by copying the input back to the host.
+
+Workloads (the paper's experiments are synthetic throughout):
+  planted spectrum  A = U diag(sigma) V^T with Haar-distributed U, V
+                    (Sec. 3.3 type 2; Sec. 5.1.1 use slatms for the same role)
+  tucker            core x_1 U_1 x_2 U_2 x_3 U_3 + noise (Sec. 5.2, Alg. 3 role)
+"""
+import math
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------- numpy
+def np_haar(n, k, rng):
+    """n x k matrix with orthonormal columns, Haar distributed: QR of a
+    Gaussian matrix with the signs of R's diagonal moved into Q."""
+    g = rng.standard_normal((n, k))
+    q, r = np.linalg.qr(g, mode="reduced")
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def np_planted(m, n, sigma, rng, noise_std=0.0):
+    """FP32 A = U diag(sigma) V^T (+ N(0, noise_std^2) noise), formed in FP64."""
+    sigma = np.asarray(sigma, np.float64)
+    k = sigma.size
+    u = np_haar(m, k, rng)
+    v = np_haar(n, k, rng)
+    a = (u * sigma[None, :]) @ v.T
+    if noise_std:
+        a = a + noise_std * rng.standard_normal((m, n))
+    return a.astype(np.float32)
+
+
+def sigma_geometric(count, ratio, first_index=1):
+    """sigma_i = ratio^i for i = first_index .. first_index + count - 1."""
+    i = np.arange(first_index, first_index + count, dtype=np.float64)
+    return ratio ** i
+
+
+def sigma_decade(count, decades, length):
+    """sigma_i = 10^(-decades * i / length), i = 1 .. count."""
+    i = np.arange(1, count + 1, dtype=np.float64)
+    return 10.0 ** (-decades * i / length)
+
+
+def np_gaussian(shape, rng, std=1.0):
+    return (std * rng.standard_normal(shape)).astype(np.float32)
+
+
+def np_uniform(shape, rng, lo=0.0, hi=1.0):
+    return rng.uniform(lo, hi, size=shape).astype(np.float32)
+
+
+def np_tucker(dims, core_dims, rng, noise_std=0.0):
+    """X = G x_1 U_1 x_2 U_2 x_3 U_3 (+ noise), G ~ U(-1, 1), U_i Haar."""
+    g = rng.uniform(-1.0, 1.0, size=core_dims)
+    x = g
+    for mode, (i_dim, j_dim) in enumerate(zip(dims, core_dims)):
+        u = np_haar(i_dim, j_dim, rng)
+        x = np.moveaxis(np.tensordot(u, x, axes=([1], [mode])), 0, mode)
+    if noise_std:
+        x = x + noise_std * rng.standard_normal(dims)
+    return x.astype(np.float32)
+
+
+def batched_problem_list(count, seed, lo=512, hi=8192, kmin=16, kmax=128):
+    """Shapes of the batched-RSVD workload: m, n log-uniform in [lo, hi],
+    planted rank k ~ U{kmin..kmax}, width r = k + max(10, ceil(k/4))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        k = int(rng.integers(kmin, kmax + 1))
+        out.append((m, n, k, k + max(10, -(-k // 4))))
+    return out
+
+
+# --------------------------------------------------------------------------- torch
+def torch_haar(n, k, gen, device):
+    import torch
+    g = torch.randn(n, k, generator=gen, device=device, dtype=torch.float64)
+    q, r = torch.linalg.qr(g, mode="reduced")
+    return q * torch.sign(torch.diagonal(r))[None, :]
+
+
+def torch_planted(m, n, sigma, seed, device, noise_std=0.0):
+    """FP32 A = U diag(sigma) V^T (+ noise) drawn and formed on ``device``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    sig = torch.as_tensor(np.asarray(sigma, np.float64), device=device)
+    k = sig.numel()
+    u = torch_haar(m, k, gen, device)
+    v = torch_haar(n, k, gen, device)
+    a = torch.empty(m, n, device=device, dtype=torch.float32)
+    rows = max(1, (1 << 28) // max(n, 1))      # form A in row blocks of <= 2 GiB FP64
+    us = u * sig[None, :]
+    vt = v.t().contiguous()
+    for r0 in range(0, m, rows):
+        blk = us[r0:r0 + rows] @ vt
+        if noise_std:
+            blk += noise_std * torch.randn(blk.shape, generator=gen, device=device,
+                                           dtype=torch.float64)
+        a[r0:r0 + rows] = blk.to(torch.float32)
+        del blk
+    del u, v, us, vt
+    return a

@@ -1,0 +1,87 @@
+"""Pins for the Gaussian matrix Omega (Sec. 3; Sec. 4.2 stores it in FP16).
+
+* FP16 magnitudes follow the exact law of RN16(g): a chi-square test of the
+  sampled binade frequencies against the exact cell probabilities, and a
+  two-sample comparison against NumPy's own Gaussian rounded by NumPy's FP16
+  cast (independent sampler, independent rounding).
+* Mean 0 (Sec. 3.2.3) and variance alpha_FP16 within sampling error.
+* FP32 Omega lies inside the FP16 cell it shares with the FP16 sample, and
+  rounds back to it except on exact cell midpoints (ties).
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import lattice, omega
+
+ALPHA16 = 0.99999995572
+
+
+def _binade(bits):
+    return ((bits.astype(np.int64) & 0x7FFF) >> 10).ravel()
+
+
+def test_zero_is_positive_and_values_finite():
+    b = omega.omega_f16_bits(3, 0, 4096, 64)
+    v = b.view(np.float16).astype(np.float64)
+    assert np.all(np.isfinite(v))
+    assert not np.any(b == 0x8000)
+    assert np.abs(v).max() < 9.09
+
+
+def test_streams_and_seeds_differ():
+    a = omega.omega_f16_bits(1, 0, 64, 64)
+    assert not np.array_equal(a, omega.omega_f16_bits(1, 1, 64, 64))
+    assert not np.array_equal(a, omega.omega_f16_bits(2, 0, 64, 64))
+    # a sub-block is the same sample as the corresponding block of a larger one
+    assert np.array_equal(a[:17, :9], omega.omega_f16_bits(1, 0, 17, 9))
+
+
+def test_f16_law_chi_square():
+    bits = omega.omega_f16_bits(11, 0, 4096, 512)     # 2M samples
+    p = lattice.cell_probabilities_f16()
+    kk = np.arange(len(p))
+    pb = np.zeros(32)
+    np.add.at(pb, kk >> 10, np.array([float(x) for x in p]))
+    obs = np.bincount(_binade(bits), minlength=32)
+    exp = pb * bits.size
+    keep = exp > 20
+    chi2 = ((obs[keep] - exp[keep]) ** 2 / exp[keep]).sum()
+    assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-4
+
+
+def test_f16_law_against_numpy_rounded_gaussian():
+    bits = omega.omega_f16_bits(12, 0, 2048, 512)
+    ref = np.random.default_rng(12).standard_normal(bits.size).astype(np.float16).view(np.uint16)
+    a = np.bincount(_binade(bits), minlength=32)
+    b = np.bincount(_binade(ref), minlength=32)
+    keep = (a + b) > 40
+    table = np.stack([a[keep], b[keep]])
+    assert stats.chi2_contingency(table)[1] > 1e-4
+    # and the signs are fair
+    s = (bits >> 15).astype(np.int64)
+    nz = (bits & 0x7FFF) != 0
+    assert abs(s[nz].mean() - 0.5) < 4 * 0.5 / np.sqrt(nz.sum())
+
+
+def test_mean_and_variance():
+    v = omega.omega_f16(21, 0, 4096, 512).astype(np.float64).ravel()
+    n = v.size
+    assert abs(v.mean()) < 4 / np.sqrt(n)
+    assert abs(v.var() - ALPHA16) < 4 * np.sqrt(2.0 / n)
+
+
+def test_f32_in_cell_and_rounds_back():
+    b16 = omega.omega_f16_bits(5, 2, 1024, 256)
+    w = omega.omega_f32(5, 2, 1024, 256)
+    k = (b16 & 0x7FFF).astype(np.int64)
+    mag = np.abs(w.astype(np.float64))
+    lower = np.where(k == 0, 0.0, lattice.f16_midpoint(np.maximum(k - 1, 0)))
+    upper = lattice.f16_midpoint(k)
+    assert np.all(mag >= lower) and np.all(mag <= upper)
+    nz = k > 0
+    assert np.all(np.signbit(w[nz]) == (b16[nz] >> 15).astype(bool))
+    back = np.abs(w).astype(np.float16).view(np.uint16)
+    tie = (mag == lower) | (mag == upper)
+    assert np.array_equal(back[~tie], k[~tie].astype(np.uint16))
+    assert tie.mean() < 1e-3
