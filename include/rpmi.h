@@ -1,0 +1,191 @@
+/*
+ * rpmi.h - mixed-precision random projection for RandNLA on AMD MI355X (gfx950).
+ *
+ * C ABI of librpmi.so.  The library computes the random projection
+ *     Y = A * Omega                                   (Sec. 2.2, eq:rp-vec)
+ * of an FP32 matrix A (m x n, or an unfolding of a tensor) by a Gaussian
+ * matrix Omega (n x r) kept in FP16, with each FP32 element of A split into an
+ * FP16 hi part and a 2^11-scaled FP16 lo part and both products run on FP16
+ * matrix cores with FP32 accumulation (Sec. 4.1, eq:shgemm-1..3).  A plain
+ * FP32 GEMM path is provided as the baseline form.
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers owned by the caller unless the
+ *     comment says "host".  No caller pointer is kept after the call returns.
+ *   - Matrices are row-major with an explicit leading dimension (elements).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it and the call returns without synchronising.
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and leave outputs untouched; the call then returns a status != RP_OK
+ *     and rp_last_error() describes it.
+ *   - Conditions found on the device (FP16 range overflow of A) are recorded
+ *     in a per-context device status word read by rp_get_device_status().
+ *   - A context must not be used from two host threads at once.
+ */
+#ifndef RPMI_H
+#define RPMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rp_ctx_s* rp_ctx;
+
+typedef enum rp_status {
+    RP_OK = 0,
+    RP_ERR_INVALID_ARG = 1,   /* bad pointer, size, stride or enum value          */
+    RP_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement      */
+    RP_ERR_RANGE = 3,         /* device: a finite |a| >= 65520 (or an infinite a)
+                                 met the FP16 split, whose hi part overflows
+                                 (Sec. 4.2: FP16 limits the exponent range of A) */
+    RP_ERR_NOT_SPD = 4,       /* device: Cholesky breakdown in CholeskyQR2        */
+    RP_ERR_NOT_CONVERGED = 5, /* device: Jacobi SVD did not converge              */
+    RP_ERR_NOMEM = 6,         /* device allocation failed                          */
+    RP_ERR_HIP = 7            /* a HIP runtime call failed (see rp_last_error)    */
+} rp_status;
+
+/* Storage format of Omega (Sec. 3: a Gaussian matrix tolerates a short mantissa). */
+typedef enum rp_omega_t {
+    RP_OMEGA_F32 = 0,         /* FP32 Gaussian                                     */
+    RP_OMEGA_F16 = 1          /* FP16 Gaussian, exact sample of RN16(N(0,1))        */
+} rp_omega_t;
+
+/* How Y = A * Omega is computed. */
+typedef enum rp_algo_t {
+    RP_ALGO_F32 = 0,          /* plain FP32 GEMM on FP32 matrix cores (baseline form);
+                                 an FP16 Omega is widened exactly to FP32 first, as
+                                 the paper does for its SGEMM comparison (Sec. 4.4.1) */
+    RP_ALGO_SPLIT_F16 = 1     /* A split into FP16 hi + 2^-11 lo on the fly, two FP16
+                                 products with FP32 accumulation (Sec. 4.1); requires
+                                 an FP16 Omega                                     */
+} rp_algo_t;
+
+/*
+ * Descriptor of the logical m x n FP32 operand A (or a tensor unfolding,
+ * Algorithm 2 line 2).  Element (i, k), 0 <= i < rows, 0 <= k < cols, is
+ *     ptr[i * s_row + (k / k_inner) * s_k_outer + (k % k_inner) * s_k_inner]
+ * A plain row-major matrix with leading dimension lda is
+ *     { ptr, m, n, lda, n, 1, 0 }.
+ * Supported by this build: s_k_inner == 1, and either k_inner == cols or
+ * k_inner a multiple of 64 dividing cols; other layouts return
+ * RP_ERR_UNSUPPORTED.  A 16-byte aligned ptr with s_row, k_inner and
+ * s_k_outer multiples of 4 takes the 16-byte load path; any other
+ * (4-byte aligned) layout is loaded element by element.
+ */
+typedef struct rp_desc {
+    const float* ptr;
+    int64_t rows;
+    int64_t cols;
+    int64_t s_row;
+    int64_t k_inner;
+    int64_t s_k_inner;
+    int64_t s_k_outer;
+} rp_desc;
+
+/* Create a context on HIP device `device`: builds the FP16 inverse-CDF
+ * threshold table on the host and uploads it, allocates the device status
+ * word.  *out receives the handle.  Makes `device` current. */
+rp_status rp_create(rp_ctx* out, int device);
+
+/* Destroy a context (synchronises the device first).  NULL is allowed. */
+rp_status rp_destroy(rp_ctx ctx);
+
+/* Static text for a status code (host string, never NULL). */
+const char* rp_status_string(rp_status s);
+
+/* Text of the last error on this context (host string owned by the context,
+ * valid until the next call on it).  Also works with ctx == NULL for errors of
+ * rp_create. */
+const char* rp_last_error(rp_ctx ctx);
+
+/*
+ * Generate the Gaussian matrix Omega (n x r, row-major, leading dimension ldo
+ * >= r) for (seed, stream_id) into `omega` (uint16 FP16 bits for
+ * RP_OMEGA_F16, float for RP_OMEGA_F32).  Sec. 3 / Sec. 4.2; the exact
+ * definition of every bit:
+ *   element (i, j) uses word j mod 4 of the Philox4x64-10 block with counter
+ *   (i, floor(j/4), stream_id, 0) and key (seed, 0); the low bit is the sign,
+ *   the upper 63 bits a uniform u.  FP16: magnitude = the FP16 value whose bit
+ *   pattern is k = #{ t : T_t <= u }, T_t = floor(2^63 erf(mu_t / sqrt 2)),
+ *   mu_t the midpoint between FP16 patterns t and t+1 (t = 0..18570); zero is
+ *   +0.  FP32: same cell k, position from the upper 32 bits f of the same word
+ *   of the block with counter word 3 = 1:
+ *   RN32(mu_{k-1} + (mu_k - mu_{k-1}) (f + 1/2) 2^-32), mu_{-1} = 0.
+ * n, r >= 0 (zero sizes enqueue nothing).
+ */
+rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
+                            int64_t n, int64_t r, rp_omega_t type,
+                            void* omega, int64_t ldo, void* stream);
+
+/*
+ * Y = A * Omega (eq:rp-vec), Y row-major m x r with leading dimension ldy >= r.
+ *   A          descriptor of the m x n operand (see rp_desc), read only.
+ *   r          number of columns of Omega and Y (r >= 0).
+ *   omega_type storage format of Omega.
+ *   seed, stream_id  used when omega == NULL: Omega is generated exactly as
+ *              rp_omega_generate would, into context-owned workspace.
+ *   omega, ldo a caller-supplied Omega (n x r row-major; FP16 bits or FP32
+ *              according to omega_type), or NULL.
+ *   algo       RP_ALGO_SPLIT_F16 (needs RP_OMEGA_F16) or RP_ALGO_F32.
+ * With RP_ALGO_SPLIT_F16 an element of A that overflows FP16 sets RP_ERR_RANGE
+ * in the device status word; Y is then unspecified.  NaN in A propagates.
+ * m, n or r equal to zero is allowed (n == 0 writes Y = 0).
+ * May grow the context workspace (device allocation, which synchronises the
+ * device when it happens).
+ */
+rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r,
+                     rp_omega_t omega_type, uint64_t seed, uint32_t stream_id,
+                     const void* omega, int64_t ldo, rp_algo_t algo,
+                     float* Y, int64_t ldy, void* stream);
+
+/*
+ * Omega in the projection kernels' fragment order, for callers that reuse one
+ * Omega across many projections (e.g. the RSVD of many matrices sharing n and
+ * r).  rp_omega_packed_size() gives the byte size of the buffer for (n, r,
+ * algo) in *bytes (host pointer).  rp_omega_pack() fills `packed` (device,
+ * caller-owned, that many bytes) from `omega` (n x r row-major, FP16 bits or
+ * FP32 by `type`) or, when omega == NULL, by generating Omega for
+ * (seed, stream_id) exactly as rp_omega_generate() does.  The split-FP16
+ * algorithm takes FP16 fragments (type must be RP_OMEGA_F16); the FP32
+ * algorithm takes FP32 fragments (an FP16 Omega is widened exactly).
+ * Zero padding beyond n rows and r columns is part of the packed buffer.
+ */
+rp_status rp_omega_packed_size(int64_t n, int64_t r, rp_algo_t algo, size_t* bytes);
+rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void* omega,
+                        int64_t ldo, rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
+                        void* packed, void* stream);
+
+/*
+ * Y = A * Omega with Omega already packed by rp_omega_pack() for the same
+ * (n = A->cols, r, algo).  Launches exactly one kernel (none if m or r is 0;
+ * a fill kernel if n is 0).  Same layout rules and device status as
+ * rp_project(); never allocates.
+ */
+rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
+                            rp_algo_t algo, float* Y, int64_t ldy, void* stream);
+
+/*
+ * Split of an FP32 array into FP16 hi and lo (Sec. 4.1, eq:shgemm-1/2), as the
+ * projection performs it in registers: hi = RN16(a), lo = RN16((a - hi) 2^11).
+ * Exposed so that the split can be checked bit for bit.  x: count floats;
+ * hi, lo: count uint16 each (device).
+ */
+rp_status rp_split_f16(rp_ctx ctx, const float* x, int64_t count,
+                       uint16_t* hi, uint16_t* lo, void* stream);
+
+/*
+ * Synchronise `stream`, then return in *out the device status word of the
+ * context as a status code (RP_OK if nothing was recorded; otherwise the
+ * first recorded condition in the order RP_ERR_RANGE, RP_ERR_NOT_SPD,
+ * RP_ERR_NOT_CONVERGED).  If `clear` is non-zero the word is reset.
+ */
+rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPMI_H */

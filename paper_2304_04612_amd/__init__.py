@@ -1,0 +1,224 @@
+"""Mixed-precision random projection for RandNLA on AMD MI355X (gfx950).
+
+Thin ctypes binding over the C ABI of ``librpmi.so`` (include/rpmi.h).  The
+functions carry the C names; they only marshal arguments (torch tensors give
+device pointers, the current torch stream gives the HIP stream).  Every step
+of the computation runs in the library's HIP kernels; there is no fallback:
+if the library is missing or fails to load, every call raises.
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librpmi.so")
+
+RP_OK = 0
+RP_ERR_INVALID_ARG = 1
+RP_ERR_UNSUPPORTED = 2
+RP_ERR_RANGE = 3
+RP_ERR_NOT_SPD = 4
+RP_ERR_NOT_CONVERGED = 5
+RP_ERR_NOMEM = 6
+RP_ERR_HIP = 7
+
+RP_OMEGA_F32 = 0
+RP_OMEGA_F16 = 1
+RP_ALGO_F32 = 0
+RP_ALGO_SPLIT_F16 = 1
+
+OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16}
+ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16}
+
+
+class RpError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+class rp_desc(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("s_row", ctypes.c_int64), ("k_inner", ctypes.c_int64),
+                ("s_k_inner", ctypes.c_int64), ("s_k_outer", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librpmi.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2304_04612_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, u64, u32, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    sig = {
+        "rp_create": [ctypes.POINTER(vp), i32],
+        "rp_destroy": [vp],
+        "rp_status_string": [i32],
+        "rp_last_error": [vp],
+        "rp_omega_generate": [vp, u64, u32, i64, i64, i32, vp, i64, vp],
+        "rp_project": [vp, ctypes.POINTER(rp_desc), i64, i32, u64, u32, vp, i64, i32, vp, i64, vp],
+        "rp_split_f16": [vp, vp, i64, vp, vp, vp],
+        "rp_omega_packed_size": [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "rp_omega_pack": [vp, u64, u32, vp, i64, i32, i64, i64, i32, vp, vp],
+        "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, vp, i64, vp],
+        "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name in ("rp_status_string", "rp_last_error") else i32
+    _lib = L
+    return L
+
+
+def status_string(s):
+    return lib().rp_status_string(int(s)).decode()
+
+
+def _check(ctx_handle, status):
+    if status != RP_OK:
+        msg = lib().rp_last_error(ctx_handle)
+        raise RpError(status, msg.decode() if msg else "")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Context:
+    """An rp_ctx on one HIP device (rp_create / rp_destroy)."""
+
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        _check(None, lib().rp_create(ctypes.byref(h), int(device)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            lib().rp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def default_context(device=None):
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default:
+        _default[dev] = Context(dev)
+    return _default[dev]
+
+
+def desc_from_tensor(a, k_inner=None, s_k_outer=0, rows=None, cols=None, s_row=None):
+    """rp_desc for a 2-D FP32 CUDA tensor with unit column stride (or an
+    explicit unfolding layout)."""
+    import torch
+    if a.dtype != torch.float32 or not a.is_cuda:
+        raise TypeError("A must be a float32 CUDA tensor")
+    if rows is None:
+        if a.dim() != 2 or a.stride(1) != 1:
+            raise ValueError("A must be 2-D with unit column stride (or give an explicit layout)")
+        rows, cols, s_row = a.shape[0], a.shape[1], a.stride(0)
+    k_inner = cols if k_inner is None else k_inner
+    return rp_desc(a.data_ptr(), rows, cols, s_row, max(k_inner, 1), 1, s_k_outer)
+
+
+def rp_omega_generate(n, r, seed, stream_id=0, omega="f16", out=None, ctx=None):
+    """Omega (n x r) for (seed, stream_id): uint16 FP16 bits or float32."""
+    import torch
+    ctx = ctx or default_context()
+    t = OMEGA_TYPES[omega]
+    if out is None:
+        out = torch.empty((n, r), dtype=torch.int16 if t == RP_OMEGA_F16 else torch.float32,
+                          device=f"cuda:{ctx.device}")
+    ldo = out.stride(0) if out.dim() == 2 and out.numel() else r
+    _check(ctx.handle, lib().rp_omega_generate(ctx.handle, seed, stream_id, n, r, t, _ptr(out),
+                                               ldo, _stream()))
+    return out
+
+
+def rp_project(a, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo="split_f16",
+               y=None, desc=None, ctx=None):
+    """Y = A Omega.  ``a``: float32 CUDA tensor (or ``desc`` for an unfolding
+    layout, with ``a`` keeping the storage alive).  ``omega``: optional
+    caller-supplied Omega (int16 FP16 bits or float32, n x r)."""
+    import torch
+    ctx = ctx or default_context()
+    d = desc if desc is not None else desc_from_tensor(a)
+    if y is None:
+        y = torch.empty((d.rows, r), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    ldy = y.stride(0) if y.numel() else max(r, 1)
+    ldo = omega.stride(0) if omega is not None and omega.numel() else max(r, 1)
+    _check(ctx.handle, lib().rp_project(ctx.handle, ctypes.byref(d), r, OMEGA_TYPES[omega_type],
+                                        seed, stream_id, _ptr(omega), ldo, ALGOS[algo], _ptr(y),
+                                        ldy, _stream()))
+    return y
+
+
+def rp_omega_packed_size(n, r, algo="split_f16"):
+    out = ctypes.c_size_t(0)
+    _check(None, lib().rp_omega_packed_size(n, r, ALGOS[algo], ctypes.byref(out)))
+    return out.value
+
+
+def rp_omega_pack(n, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo="split_f16",
+                  out=None, ctx=None):
+    """Omega in the kernels' fragment order (a uint8 device buffer)."""
+    import torch
+    ctx = ctx or default_context()
+    if out is None:
+        out = torch.empty(rp_omega_packed_size(n, r, algo), dtype=torch.uint8,
+                          device=f"cuda:{ctx.device}")
+    ldo = omega.stride(0) if omega is not None and omega.numel() else max(r, 1)
+    _check(ctx.handle, lib().rp_omega_pack(ctx.handle, seed, stream_id, _ptr(omega), ldo,
+                                           OMEGA_TYPES[omega_type], n, r, ALGOS[algo], _ptr(out),
+                                           _stream()))
+    return out
+
+
+def rp_project_packed(a, r, packed, algo="split_f16", y=None, desc=None, ctx=None):
+    """Y = A Omega with Omega from rp_omega_pack (one kernel launch)."""
+    import torch
+    ctx = ctx or default_context()
+    d = desc if desc is not None else desc_from_tensor(a)
+    if y is None:
+        y = torch.empty((d.rows, r), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    ldy = y.stride(0) if y.numel() else max(r, 1)
+    _check(ctx.handle, lib().rp_project_packed(ctx.handle, ctypes.byref(d), r, _ptr(packed),
+                                               ALGOS[algo], _ptr(y), ldy, _stream()))
+    return y
+
+
+def rp_split_f16(x, ctx=None):
+    """(hi, lo) FP16 bit patterns (int16 tensors) of the split of float32 x."""
+    import torch
+    ctx = ctx or default_context()
+    x = x.contiguous()
+    hi = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    lo = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(ctx.handle, lib().rp_split_f16(ctx.handle, _ptr(x), x.numel(), _ptr(hi), _ptr(lo), _stream()))
+    return hi, lo
+
+
+def rp_get_device_status(clear=True, ctx=None):
+    ctx = ctx or default_context()
+    out = ctypes.c_int(0)
+    _check(ctx.handle, lib().rp_get_device_status(ctx.handle, _stream(), int(clear), ctypes.byref(out)))
+    return out.value

@@ -1,0 +1,241 @@
+// Gaussian random matrix Omega on the device (Sec. 3; Sec. 4.2 keeps it in FP16).
+//
+// Random source: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), one block
+// per 4 columns of a row: element (i, j) takes word j mod 4 of the block with
+// counter (i, floor(j/4), stream_id, 0) under key (seed, 0).  Low bit = sign,
+// upper 63 bits = uniform u.  FP16: the magnitude is the FP16 pattern
+// k = #{ t : T_t <= u } (thresholds built on the host, see lattice_host.cpp),
+// so every bit is an exact integer function of (seed, stream_id, i, j) and
+// identical on any device.  FP32: the same cell k, and a position inside it
+// from the upper 32 bits of the word of the block with counter word 3 = 1;
+// one exact FP64 product, one FP64 round-to-nearest add, one RN to FP32.
+#include "rpmi_internal.h"
+
+namespace rpmi {
+namespace {
+
+constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+
+struct Words { uint64_t x[4]; };
+
+__device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd) { k0 += kW0; k1 += kW1; }
+        const uint64_t lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
+        const uint64_t lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    Words w;
+    w.x[0] = c0; w.x[1] = c1; w.x[2] = c2; w.x[3] = c3;
+    return w;
+}
+
+// k = #{ t : T_t <= u }: the guide table brackets k to one bucket of the
+// top 12 bits of u, then a binary search inside the bucket.
+__device__ __forceinline__ uint32_t f16_cell(uint64_t u, const uint64_t* __restrict__ T,
+                                             const uint32_t* __restrict__ guide) {
+    const uint32_t b = (uint32_t)(u >> (63 - kGuideLog2));
+    uint32_t lo = guide[b], hi = guide[b + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (T[mid] <= u) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint16_t f16_bits_from_word(uint64_t x, const OmegaTables& t) {
+    const uint32_t k = f16_cell(x >> 1, t.thresholds, t.guide);
+    return k == 0 ? (uint16_t)0 : (uint16_t)(k | ((uint32_t)(x & 1u) << 15));
+}
+
+// Exact value of the non-negative FP16 pattern `bits` as a double.
+__device__ __forceinline__ double f16_value(uint32_t bits) {
+    const uint32_t e = bits >> 10, m = bits & 0x3FFu;
+    if (e == 0) return (double)m * 0x1p-24;
+    return ldexp((double)(1024u + m), (int)e - 25);
+}
+
+__device__ __forceinline__ float f32_from_words(uint64_t x, uint64_t y, const OmegaTables& t) {
+    const uint32_t k = f16_cell(x >> 1, t.thresholds, t.guide);
+    const double upper = 0.5 * (f16_value(k) + f16_value(k + 1));
+    const double lower = k == 0 ? 0.0 : 0.5 * (f16_value(k - 1) + f16_value(k));
+    const double pos = ((double)(uint32_t)(y >> 32) + 0.5) * 0x1p-32;   // exact
+    const double mag = __dadd_rn(lower, __dmul_rn(upper - lower, pos));  // product exact
+    const float m32 = __double2float_rn(mag);
+    return (x & 1u) ? -m32 : m32;
+}
+
+template <bool F32>
+__global__ void omega_rowmajor_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
+                                      int64_t n, int64_t r, void* out, int64_t ldo) {
+    const int64_t nb = (r + 3) >> 2;
+    const int64_t total = n * nb;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / nb, b = q - i * nb;
+        const Words w = philox4x64_10((uint64_t)i, (uint64_t)b, stream_id, 0, seed, 0);
+        if (F32) {
+            const Words v = philox4x64_10((uint64_t)i, (uint64_t)b, stream_id, 1, seed, 0);
+            float* row = static_cast<float*>(out) + i * ldo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * b + e < r) row[4 * b + e] = f32_from_words(w.x[e], v.x[e], t);
+        } else {
+            uint16_t* row = static_cast<uint16_t*>(out) + i * ldo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * b + e < r) row[4 * b + e] = f16_bits_from_word(w.x[e], t);
+        }
+    }
+}
+
+__host__ __device__ __forceinline__ int frag_slot(int g, int e) {
+    return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4);
+}
+
+// One thread: fragment (kb, nt), lane group g, four adjacent columns c4.
+// Eight Philox blocks (the eight rows of the group's slots) give 32 values,
+// stored as the 16-byte fragments of lanes 16 g + 4 c4 + w, w = 0..3.
+__global__ void omega_packed_f16_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
+                                        int64_t n, int64_t r, uint16_t* dst,
+                                        int64_t kb_count, int64_t nt_count) {
+    const int64_t total = kb_count * nt_count * 16;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int c4 = (int)(q & 3), g = (int)((q >> 2) & 3);
+        const int64_t frag = q >> 4;                  // kb * nt_count + nt
+        const int64_t kb = frag / nt_count, nt = frag - kb * nt_count;
+        uint16_t v[4][8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t row = kb * kKBlock + frag_slot(g, e);
+            if (row < n) {
+                const Words w = philox4x64_10((uint64_t)row, (uint64_t)(nt * 4 + c4), stream_id, 0,
+                                              seed, 0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int64_t col = nt * kNTile + 4 * c4 + c;
+                    v[c][e] = col < r ? f16_bits_from_word(w.x[c], t) : (uint16_t)0;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c][e] = 0;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int lane = 16 * g + 4 * c4 + c;
+            uint4 packed;
+            packed.x = v[c][0] | ((uint32_t)v[c][1] << 16);
+            packed.y = v[c][2] | ((uint32_t)v[c][3] << 16);
+            packed.z = v[c][4] | ((uint32_t)v[c][5] << 16);
+            packed.w = v[c][6] | ((uint32_t)v[c][7] << 16);
+            *reinterpret_cast<uint4*>(dst + (frag * 64 + lane) * 8) = packed;
+        }
+    }
+}
+
+__device__ __forceinline__ float half_bits_to_float(uint16_t b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+
+// Reorder a row-major Omega (FP16 bits or FP32) into fragment order (FP16 or
+// FP32 fragments).  FP16 -> FP32 widening is exact; FP32 -> FP16 is not
+// offered.  One thread per (fragment, lane).
+template <bool SRC_F32, bool DST_F32>
+__global__ void pack_omega_kernel(const void* src, int64_t n, int64_t r, int64_t ldo, void* dst,
+                                  int64_t kb_count, int64_t nt_count) {
+    const int64_t total = kb_count * nt_count * 64;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(q & 63), g = lane >> 4, c = lane & 15;
+        const int64_t frag = q >> 6;
+        const int64_t kb = frag / nt_count, nt = frag - kb * nt_count;
+        const int64_t col = nt * kNTile + c;
+        float fv[8];
+        uint16_t hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t row = kb * kKBlock + frag_slot(g, e);
+            const bool in = row < n && col < r;
+            if (SRC_F32) {
+                fv[e] = in ? static_cast<const float*>(src)[row * ldo + col] : 0.0f;
+            } else {
+                hv[e] = in ? static_cast<const uint16_t*>(src)[row * ldo + col] : (uint16_t)0;
+                fv[e] = half_bits_to_float(hv[e]);
+            }
+        }
+        if (DST_F32) {
+            float4* d = reinterpret_cast<float4*>(static_cast<float*>(dst) + q * 8);
+            d[0] = make_float4(fv[0], fv[1], fv[2], fv[3]);
+            d[1] = make_float4(fv[4], fv[5], fv[6], fv[7]);
+        } else {
+            uint4 packed;
+            packed.x = hv[0] | ((uint32_t)hv[1] << 16);
+            packed.y = hv[2] | ((uint32_t)hv[3] << 16);
+            packed.z = hv[4] | ((uint32_t)hv[5] << 16);
+            packed.w = hv[6] | ((uint32_t)hv[7] << 16);
+            *reinterpret_cast<uint4*>(static_cast<uint16_t*>(dst) + q * 8) = packed;
+        }
+    }
+}
+
+int grid_for(int64_t total, int block) {
+    int64_t g = (total + block - 1) / block;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_omega_rowmajor(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
+                                 int64_t n, int64_t r, bool f32, void* out, int64_t ldo,
+                                 hipStream_t s) {
+    const int64_t total = n * ((r + 3) / 4);
+    if (total == 0) return hipSuccess;
+    const int block = 256, grid = grid_for(total, block);
+    if (f32)
+        hipLaunchKernelGGL(omega_rowmajor_kernel<true>, dim3(grid), dim3(block), 0, s, t, seed,
+                           stream_id, n, r, out, ldo);
+    else
+        hipLaunchKernelGGL(omega_rowmajor_kernel<false>, dim3(grid), dim3(block), 0, s, t, seed,
+                           stream_id, n, r, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
+                                   int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s) {
+    const int64_t total = dst.kb_count * dst.nt_count * 16;
+    if (total == 0) return hipSuccess;
+    const int block = 256, grid = grid_for(total, block);
+    hipLaunchKernelGGL(omega_packed_f16_kernel, dim3(grid), dim3(block), 0, s, t, seed, stream_id,
+                       n, r, static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
+                             const PackedOmega& dst, bool dst_f32, hipStream_t s) {
+    const int64_t total = dst.kb_count * dst.nt_count * 64;
+    if (total == 0) return hipSuccess;
+    const int block = 256, grid = grid_for(total, block);
+    if (src_f32 && !dst_f32) return hipErrorInvalidValue;
+    if (src_f32)
+        hipLaunchKernelGGL((pack_omega_kernel<true, true>), dim3(grid), dim3(block), 0, s, src, n,
+                           r, ldo, dst.data, dst.kb_count, dst.nt_count);
+    else if (dst_f32)
+        hipLaunchKernelGGL((pack_omega_kernel<false, true>), dim3(grid), dim3(block), 0, s, src, n,
+                           r, ldo, dst.data, dst.kb_count, dst.nt_count);
+    else
+        hipLaunchKernelGGL((pack_omega_kernel<false, false>), dim3(grid), dim3(block), 0, s, src,
+                           n, r, ldo, dst.data, dst.kb_count, dst.nt_count);
+    return hipGetLastError();
+}
+
+}  // namespace rpmi

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// librpmi.  Not part of the public ABI (include/rpmi.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpmi {
+
+// ---------------------------------------------------------------- Omega tables
+constexpr int kF16TableMax = 20000;   // threshold table capacity (18571 used)
+constexpr int kGuideLog2 = 12;        // guide table over the top 12 bits of u
+constexpr int kGuideSize = (1 << kGuideLog2) + 1;
+
+struct OmegaTables {
+    const uint64_t* thresholds;       // device, count entries
+    const uint32_t* guide;            // device, kGuideSize entries
+    int count;
+};
+
+// ---------------------------------------------------------------- packed Omega
+// The projection kernels read Omega in "fragment" order: for every block of
+// 32 contraction rows (kb) and 16 columns (nt) one fragment holds, for lane
+// l = 16 g + c of a 64-wide wave, the 8 values Omega[32 kb + slot(g, e)][16 nt + c],
+// e = 0..7, with slot(g, e) = 4 g + e for e < 4 and 16 + 4 g + (e - 4) for
+// e >= 4.  A lane of the A operand holds A[row][32 kb + slot(g, e)] for the
+// same (g, e), which makes its two 16-byte loads of A contiguous in memory.
+// Fragments are stored kb-major: frag(kb, nt) at index kb * NT + nt.
+// FP16 fragments are 64 x 8 halves (1 KiB), FP32 fragments 64 x 8 floats.
+constexpr int kKBlock = 32;           // contraction rows per fragment
+constexpr int kNTile = 16;            // columns per fragment
+
+struct PackedOmega {
+    void* data;                       // device
+    int64_t kb_count;                 // number of 32-row blocks (covers n, zero padded)
+    int64_t nt_count;                 // number of 16-column tiles (covers r, zero padded)
+};
+
+// ---------------------------------------------------------------- projection
+struct ProjArgs {
+    const float* A;
+    int64_t m, n;
+    int64_t s_row, k_inner, s_k_outer;
+    const void* omega;                // packed fragments (FP16 or FP32)
+    int64_t nt_count;                 // fragment tiles per 32-row block
+    float* Y;
+    int64_t ldy, r;
+    unsigned int* status;             // device status word
+};
+
+constexpr unsigned int kStatusRange = 1u;
+constexpr unsigned int kStatusNotSpd = 2u;
+constexpr unsigned int kStatusNotConverged = 4u;
+
+// Column padding the packed Omega must provide for each algorithm: the
+// kernels read whole column blocks.
+int64_t split_f16_col_block();
+int64_t f32_col_block();
+int64_t proj_k_block();               // contraction rows per main-loop step
+
+hipError_t launch_omega_rowmajor(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
+                                 int64_t n, int64_t r, bool f32, void* out, int64_t ldo,
+                                 hipStream_t s);
+hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
+                                   int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
+hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
+                             const PackedOmega& dst, bool dst_f32, hipStream_t s);
+hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s);
+hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s);
+hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
+                             hipStream_t s);
+hipError_t launch_fill_f32(float* y, int64_t rows, int64_t cols, int64_t ld, float v,
+                           hipStream_t s);
+
+}  // namespace rpmi
+
+extern "C" int rpmi_build_f16_thresholds(uint64_t* table, int capacity);
+extern "C" void rpmi_build_guide(const uint64_t* table, int count, uint32_t* guide, int buckets_log2);

@@ -85,3 +85,9 @@ def test_f32_in_cell_and_rounds_back():
     tie = (mag == lower) | (mag == upper)
     assert np.array_equal(back[~tie], k[~tie].astype(np.uint16))
     assert tie.mean() < 1e-3
+
+
+def test_row_subset_equals_full():
+    full = omega.omega_f16_bits(8, 1, 300, 21)
+    rows = [0, 5, 299, 17]
+    assert np.array_equal(omega.omega_f16_bits(8, 1, 0, 21, rows=rows), full[rows])
