@@ -38,9 +38,10 @@ typedef enum rp_status {
     RP_OK = 0,
     RP_ERR_INVALID_ARG = 1,   /* bad pointer, size, stride or enum value          */
     RP_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement      */
-    RP_ERR_RANGE = 3,         /* device: a finite |a| >= 65520 (or an infinite a)
-                                 met the FP16 split, whose hi part overflows
-                                 (Sec. 4.2: FP16 limits the exponent range of A) */
+    RP_ERR_RANGE = 3,         /* device: the FP16 split of A met an element whose
+                                 hi part overflows (finite |a| >= 65520; Sec. 4.2:
+                                 FP16 limits the exponent range of A) or a
+                                 non-finite element (NaN, +-inf)                  */
     RP_ERR_NOT_SPD = 4,       /* device: Cholesky breakdown in CholeskyQR2        */
     RP_ERR_NOT_CONVERGED = 5, /* device: Jacobi SVD did not converge              */
     RP_ERR_NOMEM = 6,         /* device allocation failed                          */
@@ -130,8 +131,9 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
  *   omega, ldo a caller-supplied Omega (n x r row-major; FP16 bits or FP32
  *              according to omega_type), or NULL.
  *   algo       RP_ALGO_SPLIT_F16 (needs RP_OMEGA_F16) or RP_ALGO_F32.
- * With RP_ALGO_SPLIT_F16 an element of A that overflows FP16 sets RP_ERR_RANGE
- * in the device status word; Y is then unspecified.  NaN in A propagates.
+ * With RP_ALGO_SPLIT_F16 an element of A that overflows FP16, or a non-finite
+ * element, sets RP_ERR_RANGE in the device status word; Y is then unspecified
+ * (a NaN element leaves NaN in its own row of Y).
  * m, n or r equal to zero is allowed (n == 0 writes Y = 0).
  * May grow the context workspace (device allocation, which synchronises the
  * device when it happens).

@@ -40,26 +40,54 @@ struct Tile {
     static constexpr int NTB = BN / kNTile;
 };
 
-using SplitTile = Tile<2, 2, 2, 8, 2>;   // 64 x 256 outputs, 64-deep steps
+using SplitTile = Tile<2, 2, 2, 8, 1>;   // 64 x 256 outputs, 32-deep steps
+constexpr int kSplitDepth = 6;           // pipeline stages (A registers, Omega LDS stages)
 using F32Tile = Tile<2, 2, 4, 4, 1>;     // 128 x 128 outputs, 32-deep steps
+constexpr int kF32Depth = 3;
 
 // ------------------------------------------------------------------ split
-__device__ __forceinline__ void split_one(float a, _Float16& hi, _Float16& lo) {
-    hi = (_Float16)a;                                   // RN to FP16
-    lo = (_Float16)((a - (float)hi) * 2048.0f);        // exact difference, exact scaling, RN
+// Two elements at a time: hi = RN16(a) for both with one v_cvt_pk_f16_f32,
+// then lo = RN16(2^11 a - 2^11 hi) with v_fma_mix{lo,hi}_f16 reading hi as an
+// FP16 half of the packed register.  2^11 a is exact in FP32 and so is the
+// fused 2^11 a - 2^11 hi (a - hi is exact), so the only rounding of lo is the
+// final RN16, exactly eq:shgemm-2.  2.5 VALU instructions per element.
+__device__ __forceinline__ void split_pair(float a0, float a1, uint32_t& hi2, uint32_t& lo2) {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t h = {(_Float16)a0, (_Float16)a1};
+    hi2 = __builtin_bit_cast(uint32_t, h);
+    const float t0 = a0 * 2048.0f, t1 = a1 * 2048.0f;
+    const float m = -2048.0f;
+    uint32_t lo;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(hi2), "v"(m), "v"(t0));
+    asm("v_fma_mixhi_f16 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "+v"(lo) : "v"(hi2), "v"(m), "v"(t1));
+    lo2 = lo;
 }
 
-__device__ __forceinline__ void split8(const floatx4& a0, const floatx4& a1, half8& hi, half8& lo,
-                                       float& amax) {
+__device__ __forceinline__ void split8(const floatx4& a0, const floatx4& a1, half8& hi, half8& lo) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+    split_pair(a0[0], a0[1], h0, l0);
+    split_pair(a0[2], a0[3], h1, l1);
+    split_pair(a1[0], a1[1], h2, l2);
+    split_pair(a1[2], a1[3], h3, l3);
+    hi = __builtin_bit_cast(half8, u32x4{h0, h1, h2, h3});
+    lo = __builtin_bit_cast(half8, u32x4{l0, l1, l2, l3});
+}
+
+// An element whose hi part overflows FP16 (finite |a| >= 65520), or a
+// non-finite element, gives a non-finite lo part; multiplied by any Omega
+// value (0 included) it leaves the lo accumulators of its whole row
+// non-finite, and for in-range finite A they never are (|lo| <= 2^11 ulp(a)).
+// So one check of the lo accumulators after the loop detects the condition.
+template <int TM, int TN>
+__device__ __forceinline__ bool any_nonfinite(const floatx4 (&acc)[TM][TN]) {
+    float s = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        _Float16 h, l;
-        split_one(a0[e], h, l);
-        hi[e] = h; lo[e] = l;
-        split_one(a1[e], h, l);
-        hi[4 + e] = h; lo[4 + e] = l;
-        amax = fmaxf(amax, fmaxf(fabsf(a0[e]), fabsf(a1[e])));
-    }
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) s += (acc[tm][j][0] + acc[tm][j][1]) + (acc[tm][j][2] + acc[tm][j][3]);
+    return !__builtin_isfinite(s * 0.0f);
 }
 
 // ------------------------------------------------------------------ A loads
@@ -96,8 +124,44 @@ __device__ __forceinline__ int64_t step_offset(int64_t k0, int64_t k_inner, int6
     return o * s_k_outer + (k0 - o * k_inner);
 }
 
-// ------------------------------------------------------------------ split-FP16 kernel
+// A register ring: the loads of step `it` land in ring slot it mod D and are
+// issued D - 1 steps before they are consumed, so D - 1 steps of A stay in
+// flight per wave.  The last step is loaded with per-element guards when the
+// contraction length is not a multiple of the step.
 template <class T, bool VEC>
+struct AStream {
+    const float* arow[T::TM];
+    int64_t n, k_inner, s_k_outer, nsteps;
+    int g;
+    bool tail;
+
+    __device__ __forceinline__ void issue(floatx4 (&dst)[T::TM][T::KS][2], int64_t it) const {
+        if (it >= nsteps) return;
+        const int64_t k0 = it * T::BK;
+        const int64_t off = step_offset(k0, k_inner, s_k_outer);
+        if (tail && it + 1 == nsteps) load_a<T, true, VEC>(dst, arow, off, k0, n, g);
+        else load_a<T, false, VEC>(dst, arow, off, k0, n, g);
+    }
+};
+
+template <class T, bool VEC>
+__device__ __forceinline__ AStream<T, VEC> make_astream(const ProjArgs& p, int64_t bm, int wm, int c, int g) {
+    AStream<T, VEC> s;
+#pragma unroll
+    for (int tm = 0; tm < T::TM; ++tm) {
+        int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + c;
+        row = row < p.m ? row : p.m - 1;
+        s.arow[tm] = p.A + row * p.s_row;
+    }
+    s.n = p.n; s.k_inner = p.k_inner; s.s_k_outer = p.s_k_outer;
+    s.nsteps = (p.n + T::BK - 1) / T::BK;
+    s.g = g;
+    s.tail = (p.n % T::BK) != 0;
+    return s;
+}
+
+// ------------------------------------------------------------------ split-FP16 kernel
+template <class T, int D, bool VEC>
 __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjArgs p) {
     __shared__ half8 lds[2][T::KS * T::NTB * 64];
 
@@ -107,16 +171,8 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
     const int wm = wave % T::WM, wn = wave / T::WM;
     const int64_t bm = blockIdx.x, bn = blockIdx.y;
 
-    const float* arow[T::TM];
-#pragma unroll
-    for (int tm = 0; tm < T::TM; ++tm) {
-        int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + c;
-        row = row < p.m ? row : p.m - 1;
-        arow[tm] = p.A + row * p.s_row;
-    }
-
-    const int64_t nsteps = (p.n + T::BK - 1) / T::BK;
-    const bool tail = (p.n % T::BK) != 0;
+    const AStream<T, VEC> as = make_astream<T, VEC>(p, bm, wm, c, g);
+    const int64_t nsteps = as.nsteps;
     const half8* om = static_cast<const half8*>(p.omega);
 
     constexpr int CH = T::KS * T::NTB * 64 / T::THREADS;   // 16-byte chunks per thread
@@ -135,65 +191,56 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
             acc_hi[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
             acc_lo[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    float amax = 0.0f;
 
-    floatx4 abuf[2][T::TM][T::KS][2];
+    floatx4 ring[D][T::TM][T::KS][2];
     half8 ostage[CH];
 
-    // prologue: step 0
-    if (nsteps == 1 && tail)
-        load_a<T, true, VEC>(abuf[0], arow, step_offset(0, p.k_inner, p.s_k_outer), 0, p.n, g);
-    else
-        load_a<T, false, VEC>(abuf[0], arow, step_offset(0, p.k_inner, p.s_k_outer), 0, p.n, g);
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s) as.issue(ring[s], s);
 #pragma unroll
     for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(0, i);
 #pragma unroll
     for (int i = 0; i < CH; ++i) lds[0][tid + i * T::THREADS] = ostage[i];
     __syncthreads();
 
-    auto step = [&](int64_t it, floatx4 (&cur)[T::TM][T::KS][2], floatx4 (&nxt)[T::TM][T::KS][2]) {
-        const int buf = (int)(it & 1);
-        const bool more = it + 1 < nsteps;
-        if (more) {
-            const int64_t k1 = (it + 1) * T::BK;
-            const int64_t off = step_offset(k1, p.k_inner, p.s_k_outer);
-            if (tail && it + 2 == nsteps)
-                load_a<T, true, VEC>(nxt, arow, off, k1, p.n, g);
-            else
-                load_a<T, false, VEC>(nxt, arow, off, k1, p.n, g);
+    for (int64_t it0 = 0; it0 < nsteps; it0 += D) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(it + 1, i);
-        }
+        for (int s = 0; s < D; ++s) {
+            const int64_t it = it0 + s;
+            if (it < nsteps) {
+                as.issue(ring[(s + D - 1) % D], it + D - 1);
+                const bool more = it + 1 < nsteps;
+                if (more) {
 #pragma unroll
-        for (int kb = 0; kb < T::KS; ++kb) {
-            half8 hi[T::TM], lo[T::TM];
-#pragma unroll
-            for (int tm = 0; tm < T::TM; ++tm) split8(cur[tm][kb][0], cur[tm][kb][1], hi[tm], lo[tm], amax);
-#pragma unroll
-            for (int j = 0; j < T::TN; ++j) {
-                const half8 b = lds[buf][(kb * T::NTB + wn * T::TN + j) * 64 + lane];
-#pragma unroll
-                for (int tm = 0; tm < T::TM; ++tm) {
-                    acc_hi[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[tm], b, acc_hi[tm][j], 0, 0, 0);
-                    acc_lo[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[tm], b, acc_lo[tm][j], 0, 0, 0);
+                    for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(it + 1, i);
                 }
+                const int buf = (int)(it & 1);
+#pragma unroll
+                for (int kb = 0; kb < T::KS; ++kb) {
+                    half8 hi[T::TM], lo[T::TM];
+#pragma unroll
+                    for (int tm = 0; tm < T::TM; ++tm)
+                        split8(ring[s][tm][kb][0], ring[s][tm][kb][1], hi[tm], lo[tm]);
+#pragma unroll
+                    for (int j = 0; j < T::TN; ++j) {
+                        const half8 b = lds[buf][(kb * T::NTB + wn * T::TN + j) * 64 + lane];
+#pragma unroll
+                        for (int tm = 0; tm < T::TM; ++tm) {
+                            acc_hi[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[tm], b, acc_hi[tm][j], 0, 0, 0);
+                            acc_lo[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[tm], b, acc_lo[tm][j], 0, 0, 0);
+                        }
+                    }
+                }
+                if (more) {
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) lds[buf ^ 1][tid + i * T::THREADS] = ostage[i];
+                }
+                __syncthreads();
             }
         }
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < CH; ++i) lds[buf ^ 1][tid + i * T::THREADS] = ostage[i];
-        }
-        __syncthreads();
-    };
-
-    int64_t it = 0;
-    for (; it + 1 < nsteps; it += 2) {
-        step(it, abuf[0], abuf[1]);
-        step(it + 1, abuf[1], abuf[0]);
     }
-    if (it < nsteps) step(it, abuf[0], abuf[1]);
 
-    if (amax >= 65520.0f) atomicOr(p.status, kStatusRange);
+    if (any_nonfinite(acc_lo)) atomicOr(p.status, kStatusRange);
 
     // epilogue: Y = acc_hi + 2^-11 acc_lo; lane (g, c) holds rows 4g..4g+3 of column c
 #pragma unroll
@@ -210,8 +257,240 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
         }
 }
 
+// ------------------------------------------------------------------ split-FP16, deep pipeline
+// The fast path for 16-byte aligned A.
+//  * Omega reaches LDS by direct global->LDS loads (no register staging) into
+//    a ring of D stages; A reaches registers through a ring of D steps.
+//  * The split of step it+1 is computed while the MFMAs of step it run (two
+//    sets of hi/lo registers), so the VALU work of the split hides under the
+//    matrix-core work instead of adding to it.
+//  * Every pipelined step issues exactly the same memory instructions (steps
+//    past the end re-load the last full step into a slot nobody reads), so
+//    the count of memory operations between two points is fixed and the waits
+//    are exact vmcnt values: at the top of step it, everything issued before
+//    the loads of step it+2 must have landed (that is: A of step it+1 for the
+//    split that runs during this step, and this step's Omega stage), i.e. at
+//    most D-3 steps' worth of operations may remain pending.
+//  * A contraction tail shorter than a step is computed after the pipeline
+//    drains, with guarded register loads.
+#define RPMI_INLINE __attribute__((always_inline))
+#define RPMI_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+#define RPMI_GLB(p) ((__attribute__((address_space(1))) void*)(p))
+
+template <int I>
+struct IntC { static constexpr int value = I; };
+
+template <int N, class F, int I = 0>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(IntC<I>{});
+        static_for<N, F, I + 1>(static_cast<F&&>(f));
+    }
+}
+
+// s_waitcnt immediate for "at most N vector-memory operations pending":
+// vmcnt in bits [3:0] and [15:14]; expcnt and lgkmcnt at their maxima.
+template <int N>
+struct VmCnt {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    static constexpr int value = (N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+};
+
+// Wait until at most N vector-memory operations of this wave are pending,
+// then a workgroup barrier.  The empty asm statements keep the compiler from
+// moving memory accesses across.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(VmCnt<N>::value);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// scheduling-group masks of __builtin_amdgcn_sched_group_barrier
+constexpr int kSchedValu = 0x002, kSchedMfma = 0x008, kSchedVmemRead = 0x020, kSchedDsRead = 0x100;
+
+template <class T, int D>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(ProjArgs p) {
+    constexpr int STAGE = T::KS * T::NTB * 64;                 // 16-byte chunks per Omega stage
+    constexpr int CH = STAGE / T::THREADS;                     // chunks per thread per stage
+    constexpr int A_OPS = T::TM * T::KS * 2;                   // 16-byte A loads per step
+    constexpr int OPS = CH + A_OPS;                            // memory instructions per issue
+    static_assert(CH * T::THREADS == STAGE, "Omega stage must split evenly");
+    static_assert(D >= 4 && D % 2 == 0, "pipeline depth: even, >= 4");
+    static_assert((D - 3) * OPS < 64, "vmcnt range");
+    __shared__ half8 lds[D][STAGE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int wm = wave % T::WM, wn = wave / T::WM;
+    const int64_t bm = blockIdx.x, bn = blockIdx.y;
+    const int64_t nfull = p.n / T::BK;
+
+    // A: per-lane row pointer (its 16-byte column group folded in); per step a
+    // uniform contraction offset, advanced without divisions.
+    const char* abase[T::TM];
+#pragma unroll
+    for (int tm = 0; tm < T::TM; ++tm) {
+        int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + c;
+        row = row < p.m ? row : p.m - 1;
+        abase[tm] = reinterpret_cast<const char*>(p.A + row * p.s_row) + 16 * g;
+    }
+    int64_t ioff = 0, irun = 0, iin = 0;       // element offset of the next step to issue
+    // Omega: per-thread byte offset of its chunks inside one step's block;
+    // the step's base address is uniform.
+    const char* ombase = static_cast<const char*>(p.omega);
+    const int64_t ostep = (int64_t)T::KS * p.nt_count * 64 * 16;   // bytes per step
+    uint32_t ovoff[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const int q = tid + i * T::THREADS;
+        const int kbl = q / (T::NTB * 64), jn = (q / 64) % T::NTB, ql = q % 64;
+        ovoff[i] = (uint32_t)(((kbl * p.nt_count + bn * T::NTB + jn) * 64 + ql) * 16);
+    }
+
+    floatx4 acc_hi[T::TM][T::TN], acc_lo[T::TM][T::TN];
+#pragma unroll
+    for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) {
+            acc_hi[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc_lo[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    floatx4 ring[D][T::TM][T::KS][2];
+    half8 hs[2][T::TM][T::KS], ls[2][T::TM][T::KS];   // split of the current / next step
+
+    // Issue step j (clamped to the last full step): Omega stage -> lds[slot]
+    // direct, then A -> ring[slot].
+    auto issue = [&](int64_t j, auto slot_c) RPMI_INLINE {
+        constexpr int slot = decltype(slot_c)::value;
+        const bool real = j < nfull;
+        j = real ? j : nfull - 1;
+        const char* osrc = ombase + j * ostep;
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            __builtin_amdgcn_global_load_lds(RPMI_GLB(osrc + ovoff[i]),
+                                             RPMI_LDS(&lds[slot][wave * 64 + i * T::THREADS]), 16, 0, 0);
+        const int64_t boff = ioff * 4;
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int kb = 0; kb < T::KS; ++kb)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    ring[slot][tm][kb][h] = *reinterpret_cast<const floatx4*>(
+                        abase[tm] + boff + (kb * kKBlock + h * 16) * 4);
+        if (j + 1 < nfull) {
+            iin += T::BK;
+            const bool wrap = iin >= p.k_inner;
+            irun += wrap ? p.s_k_outer : 0;
+            iin = wrap ? 0 : iin;
+            ioff = irun + iin;
+        }
+    };
+
+    auto split_step = [&](const floatx4 (&a)[T::TM][T::KS][2], half8 (&h)[T::TM][T::KS],
+                          half8 (&l)[T::TM][T::KS]) RPMI_INLINE {
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int kb = 0; kb < T::KS; ++kb) split8(a[tm][kb][0], a[tm][kb][1], h[tm][kb], l[tm][kb]);
+    };
+
+    auto mfma_step = [&](const half8 (&h)[T::TM][T::KS], const half8 (&l)[T::TM][T::KS],
+                         const half8* stage) RPMI_INLINE {
+#pragma unroll
+        for (int kb = 0; kb < T::KS; ++kb) {
+            half8 b[T::TN];
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j) b[j] = stage[(kb * T::NTB + wn * T::TN + j) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+                for (int tm = 0; tm < T::TM; ++tm) {
+                    acc_hi[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(h[tm][kb], b[j], acc_hi[tm][j], 0, 0, 0);
+                    acc_lo[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(l[tm][kb], b[j], acc_lo[tm][j], 0, 0, 0);
+                }
+        }
+    };
+
+    // One pipelined step in slot s: wait + barrier, issue step it+D-1, then the
+    // MFMAs of step it (split already done) interleaved with the split of
+    // step it+1.  The wait and the barrier are one asm statement with a memory
+    // clobber so that no LDS access moves across.
+    auto step = [&](int64_t it, auto slot_c) RPMI_INLINE {
+        constexpr int s = decltype(slot_c)::value;
+        constexpr int cur = s & 1;
+        wait_vm_barrier<(D - 3) * OPS>();
+        issue(it + D - 1, IntC<(s + D - 1) % D>{});
+        mfma_step(hs[cur], ls[cur], lds[s]);
+        split_step(ring[(s + 1) % D], hs[cur ^ 1], ls[cur ^ 1]);
+        // interleave: Omega fragment reads up front, then one MFMA per
+        // group of split instructions
+        __builtin_amdgcn_sched_group_barrier(kSchedVmemRead, OPS, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, T::TN, 0);
+#pragma unroll
+        for (int q = 0; q < 2 * T::TM * T::TN * T::KS; ++q) {
+            __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(kSchedValu, 2, 0);
+            if (q == T::TM * T::TN) __builtin_amdgcn_sched_group_barrier(kSchedDsRead, T::TN, 0);
+        }
+    };
+
+    if (nfull > 0) {
+        static_for<D - 1>([&](auto sc) RPMI_INLINE { issue(decltype(sc)::value, sc); });
+        // A of step 0 is followed by D-2 issues
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(VmCnt<(D - 2) * OPS>::value);
+        split_step(ring[0], hs[0], ls[0]);
+        const int64_t ngroups = nfull / D;
+        for (int64_t grp = 0; grp < ngroups; ++grp) {
+            const int64_t it0 = grp * D;
+            static_for<D>([&](auto sc) RPMI_INLINE { step(it0 + decltype(sc)::value, sc); });
+        }
+        const int64_t it0 = ngroups * D;
+        static_for<D>([&](auto sc) RPMI_INLINE {
+            if (it0 + decltype(sc)::value < nfull) step(it0 + decltype(sc)::value, sc);
+        });
+        wait_vm_barrier<0>();
+    }
+
+    if (nfull * T::BK < p.n) {   // contraction tail: guarded loads, zero-padded Omega rows
+        const AStream<T, true> as = make_astream<T, true>(p, bm, wm, c, g);
+        floatx4 a[T::TM][T::KS][2];
+        const int64_t k0 = nfull * T::BK;
+        load_a<T, true, true>(a, as.arow, step_offset(k0, p.k_inner, p.s_k_outer), k0, p.n, g);
+        const half8* om = static_cast<const half8*>(p.omega);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int q = tid + i * T::THREADS;
+            const int kbl = q / (T::NTB * 64), jn = (q / 64) % T::NTB, ql = q % 64;
+            lds[0][q] = om[((nfull * T::KS + kbl) * p.nt_count + bn * T::NTB + jn) * 64 + ql];
+        }
+        __syncthreads();
+        split_step(a, hs[0], ls[0]);
+        mfma_step(hs[0], ls[0], lds[0]);
+    }
+
+    if (any_nonfinite(acc_lo)) atomicOr(p.status, kStatusRange);
+
+#pragma unroll
+    for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) {
+            const int64_t col = bn * T::BN + (wn * T::TN + j) * 16 + c;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + 4 * g + e;
+                if (row < p.m && col < p.r)
+                    p.Y[row * p.ldy + col] = acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f;
+            }
+        }
+}
+
 // ------------------------------------------------------------------ FP32 kernel
-template <class T, bool VEC>
+template <class T, int D, bool VEC>
 __global__ __launch_bounds__(T::THREADS, 1) void project_f32_kernel(ProjArgs p) {
     // FP32 fragments: 8 floats per lane = two 16-byte halves
     __shared__ floatx4 lds[2][T::KS * T::NTB * 64 * 2];
@@ -222,16 +501,8 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_f32_kernel(ProjArgs p) 
     const int wm = wave % T::WM, wn = wave / T::WM;
     const int64_t bm = blockIdx.x, bn = blockIdx.y;
 
-    const float* arow[T::TM];
-#pragma unroll
-    for (int tm = 0; tm < T::TM; ++tm) {
-        int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + c;
-        row = row < p.m ? row : p.m - 1;
-        arow[tm] = p.A + row * p.s_row;
-    }
-
-    const int64_t nsteps = (p.n + T::BK - 1) / T::BK;
-    const bool tail = (p.n % T::BK) != 0;
+    const AStream<T, VEC> as = make_astream<T, VEC>(p, bm, wm, c, g);
+    const int64_t nsteps = as.nsteps;
     const floatx4* om = static_cast<const floatx4*>(p.omega);
 
     constexpr int CH = T::KS * T::NTB * 64 * 2 / T::THREADS;
@@ -248,63 +519,55 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_f32_kernel(ProjArgs p) 
 #pragma unroll
         for (int j = 0; j < T::TN; ++j) acc[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    floatx4 abuf[2][T::TM][T::KS][2];
+    floatx4 ring[D][T::TM][T::KS][2];
     floatx4 ostage[CH];
 
-    if (nsteps == 1 && tail)
-        load_a<T, true, VEC>(abuf[0], arow, step_offset(0, p.k_inner, p.s_k_outer), 0, p.n, g);
-    else
-        load_a<T, false, VEC>(abuf[0], arow, step_offset(0, p.k_inner, p.s_k_outer), 0, p.n, g);
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s) as.issue(ring[s], s);
 #pragma unroll
     for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(0, i);
 #pragma unroll
     for (int i = 0; i < CH; ++i) lds[0][tid + i * T::THREADS] = ostage[i];
     __syncthreads();
 
-    auto step = [&](int64_t it, floatx4 (&cur)[T::TM][T::KS][2], floatx4 (&nxt)[T::TM][T::KS][2]) {
-        const int buf = (int)(it & 1);
-        const bool more = it + 1 < nsteps;
-        if (more) {
-            const int64_t k1 = (it + 1) * T::BK;
-            const int64_t off = step_offset(k1, p.k_inner, p.s_k_outer);
-            if (tail && it + 2 == nsteps)
-                load_a<T, true, VEC>(nxt, arow, off, k1, p.n, g);
-            else
-                load_a<T, false, VEC>(nxt, arow, off, k1, p.n, g);
+    for (int64_t it0 = 0; it0 < nsteps; it0 += D) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(it + 1, i);
-        }
+        for (int s = 0; s < D; ++s) {
+            const int64_t it = it0 + s;
+            if (it < nsteps) {
+                as.issue(ring[(s + D - 1) % D], it + D - 1);
+                const bool more = it + 1 < nsteps;
+                if (more) {
 #pragma unroll
-        for (int kb = 0; kb < T::KS; ++kb) {
-            floatx4 b[T::TN][2];
+                    for (int i = 0; i < CH; ++i) ostage[i] = *omega_src(it + 1, i);
+                }
+                const int buf = (int)(it & 1);
 #pragma unroll
-            for (int j = 0; j < T::TN; ++j) {
-                const int f = ((kb * T::NTB + wn * T::TN + j) * 64 + lane) * 2;
-                b[j][0] = lds[buf][f];
-                b[j][1] = lds[buf][f + 1];
+                for (int kb = 0; kb < T::KS; ++kb) {
+                    floatx4 b[T::TN][2];
+#pragma unroll
+                    for (int j = 0; j < T::TN; ++j) {
+                        const int f = ((kb * T::NTB + wn * T::TN + j) * 64 + lane) * 2;
+                        b[j][0] = lds[buf][f];
+                        b[j][1] = lds[buf][f + 1];
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+#pragma unroll
+                        for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+                            for (int tm = 0; tm < T::TM; ++tm)
+                                acc[tm][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    ring[s][tm][kb][t >> 2][t & 3], b[j][t >> 2][t & 3], acc[tm][j], 0, 0, 0);
+                }
+                if (more) {
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) lds[buf ^ 1][tid + i * T::THREADS] = ostage[i];
+                }
+                __syncthreads();
             }
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-#pragma unroll
-                for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-                    for (int tm = 0; tm < T::TM; ++tm)
-                        acc[tm][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            cur[tm][kb][t >> 2][t & 3], b[j][t >> 2][t & 3], acc[tm][j], 0, 0, 0);
         }
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < CH; ++i) lds[buf ^ 1][tid + i * T::THREADS] = ostage[i];
-        }
-        __syncthreads();
-    };
-
-    int64_t it = 0;
-    for (; it + 1 < nsteps; it += 2) {
-        step(it, abuf[0], abuf[1]);
-        step(it + 1, abuf[1], abuf[0]);
     }
-    if (it < nsteps) step(it, abuf[0], abuf[1]);
 
 #pragma unroll
     for (int tm = 0; tm < T::TM; ++tm)
@@ -321,12 +584,18 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_f32_kernel(ProjArgs p) 
 
 // ------------------------------------------------------------------ small kernels
 __global__ void split_dump_kernel(const float* x, int64_t count, uint16_t* hi, uint16_t* lo) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        _Float16 h, l;
-        split_one(x[i], h, l);
-        hi[i] = __builtin_bit_cast(uint16_t, h);
-        lo[i] = __builtin_bit_cast(uint16_t, l);
+    // the projection kernels' own split, two elements per thread
+    for (int64_t i = 2 * (blockIdx.x * (int64_t)blockDim.x + threadIdx.x); i < count;
+         i += 2 * (int64_t)gridDim.x * blockDim.x) {
+        const float a0 = x[i], a1 = i + 1 < count ? x[i + 1] : 0.0f;
+        uint32_t h, l;
+        split_pair(a0, a1, h, l);
+        hi[i] = (uint16_t)h;
+        lo[i] = (uint16_t)l;
+        if (i + 1 < count) {
+            hi[i + 1] = (uint16_t)(h >> 16);
+            lo[i + 1] = (uint16_t)(l >> 16);
+        }
     }
 }
 
@@ -361,9 +630,9 @@ hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
     using T = SplitTile;
     dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN));
     if (vector_ok(a))
-        hipLaunchKernelGGL((project_split_f16_kernel<T, true>), grid, dim3(T::THREADS), 0, s, a);
+        hipLaunchKernelGGL((project_split_f16_dma_kernel<T, kSplitDepth>), grid, dim3(T::THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((project_split_f16_kernel<T, false>), grid, dim3(T::THREADS), 0, s, a);
+        hipLaunchKernelGGL((project_split_f16_kernel<T, kSplitDepth, false>), grid, dim3(T::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -371,9 +640,9 @@ hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {
     using T = F32Tile;
     dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN));
     if (vector_ok(a))
-        hipLaunchKernelGGL((project_f32_kernel<T, true>), grid, dim3(T::THREADS), 0, s, a);
+        hipLaunchKernelGGL((project_f32_kernel<T, kF32Depth, true>), grid, dim3(T::THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((project_f32_kernel<T, false>), grid, dim3(T::THREADS), 0, s, a);
+        hipLaunchKernelGGL((project_f32_kernel<T, kF32Depth, false>), grid, dim3(T::THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -128,18 +128,32 @@ def test_empty_sizes():
 
 
 def test_range_flag_and_nan():
+    """An element outside the FP16 range of the split (Sec. 4.2) sets
+    RP_ERR_RANGE; so does a non-finite element (its split is non-finite too).
+    NaN propagates to its own row only."""
     m = rp()
     m.rp_get_device_status(clear=True)
     a = np.ones((70, 90), np.float32)
-    assert m.rp_project(dev(a), 20) is not None
+    a[3, 4] = 65519.0                      # largest value whose RN16 is finite
+    m.rp_project(dev(a), 20)
     assert m.rp_get_device_status(clear=True) == m.RP_OK
-    a[33, 44] = 70000.0
+    a[33, 44] = 65520.0
+    m.rp_project(dev(a), 20)
+    assert m.rp_get_device_status(clear=True) == m.RP_ERR_RANGE
+    a = np.ones((70, 90), np.float32)
+    a[33, 44] = -1e30
     m.rp_project(dev(a), 20)
     assert m.rp_get_device_status(clear=True) == m.RP_ERR_RANGE
     a = np.ones((70, 90), np.float32)
     a[5, 6] = np.nan
     y = host(m.rp_project(dev(a), 20))
     assert np.all(np.isnan(y[5])) and np.all(np.isfinite(np.delete(y, 5, axis=0)))
+    assert m.rp_get_device_status(clear=True) == m.RP_ERR_RANGE
+    # the FP32 path has no FP16 range limit
+    a = np.ones((70, 90), np.float32)
+    a[33, 44] = 1e30
+    y = host(m.rp_project(dev(a), 20, algo="f32"))
+    assert np.all(np.isfinite(y))
     assert m.rp_get_device_status(clear=True) == m.RP_OK
 
 
