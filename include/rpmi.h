@@ -162,9 +162,13 @@ rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const voi
 
 /*
  * Y = A * Omega with Omega already packed by rp_omega_pack() for the same
- * (n = A->cols, r, algo).  Launches exactly one kernel (none if m or r is 0;
- * a fill kernel if n is 0).  Same layout rules and device status as
- * rp_project(); never allocates.
+ * (n = A->cols, r, algo).  Launches one projection kernel (none if m or r is
+ * 0; a fill kernel if n is 0).  Same layout rules and device status as
+ * rp_project().  When the output tiles of the split-FP16 path do not fill the
+ * device, the contraction is split across workgroups whose partial sums live
+ * in a context-owned workspace; growing it (first use of a shape) allocates
+ * and synchronises the device.  Launches that share a context must not run
+ * concurrently on different streams.
  */
 rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
                             rp_algo_t algo, float* Y, int64_t ldy, void* stream);

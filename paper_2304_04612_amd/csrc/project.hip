@@ -40,8 +40,12 @@ struct Tile {
     static constexpr int NTB = BN / kNTile;
 };
 
-using SplitTile = Tile<2, 2, 2, 8, 1>;   // 64 x 256 outputs, 32-deep steps
-constexpr int kSplitDepth = 6;           // pipeline stages (A registers, Omega LDS stages)
+using SplitTile = Tile<2, 2, 2, 8, 2>;   // general split path: 64 x 256 outputs, 64-deep steps
+constexpr int kSplitDepth = 3;
+using DmaTile = Tile<4, 1, 2, 16, 1>;    // fast path: 128 x 256 outputs, 32-deep steps, each
+                                         // wave owns 32 rows (A read once per workgroup)
+constexpr int kDmaDepth = 6;             // pipeline stages (A registers, Omega LDS stages)
+constexpr bool kDmaTwoAcc = false;       // one accumulator (hi against 2^11 Omega); two spill at BM = 128
 using F32Tile = Tile<2, 2, 4, 4, 1>;     // 128 x 128 outputs, 32-deep steps
 constexpr int kF32Depth = 3;
 
@@ -73,6 +77,15 @@ __device__ __forceinline__ void split8(const floatx4& a0, const floatx4& a1, hal
     split_pair(a1[2], a1[3], h3, l3);
     hi = __builtin_bit_cast(half8, u32x4{h0, h1, h2, h3});
     lo = __builtin_bit_cast(half8, u32x4{l0, l1, l2, l3});
+}
+
+// Single accumulator: Y = 2^-11 * sum(hi * (2^11 Omega) + lo * Omega), which
+// is eq:shgemm-3 with the 2^-11 applied once in the epilogue.  2^11 Omega is
+// exact in FP16 for |omega| < 32 (the Gaussian lattice stops at 9.09); a
+// larger entry becomes inf and is reported like an A element out of range.
+__device__ __forceinline__ half8 scale_2p11(const half8& b) {
+    const _Float16 k = (_Float16)2048.0f;
+    return b * half8{k, k, k, k, k, k, k, k};
 }
 
 // An element whose hi part overflows FP16 (finite |a| >= 65520), or a
@@ -310,7 +323,7 @@ __device__ __forceinline__ void wait_vm_barrier() {
 // scheduling-group masks of __builtin_amdgcn_sched_group_barrier
 constexpr int kSchedValu = 0x002, kSchedMfma = 0x008, kSchedVmemRead = 0x020, kSchedDsRead = 0x100;
 
-template <class T, int D>
+template <class T, int D, bool TWO_ACC>
 __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(ProjArgs p) {
     constexpr int STAGE = T::KS * T::NTB * 64;                 // 16-byte chunks per Omega stage
     constexpr int CH = STAGE / T::THREADS;                     // chunks per thread per stage
@@ -318,18 +331,41 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
     constexpr int OPS = CH + A_OPS;                            // memory instructions per issue
     static_assert(CH * T::THREADS == STAGE, "Omega stage must split evenly");
     static_assert(D >= 4 && D % 2 == 0, "pipeline depth: even, >= 4");
-    static_assert((D - 3) * OPS < 64, "vmcnt range");
-    __shared__ half8 lds[D][STAGE];
+    static_assert((D - 2) * OPS < 64, "vmcnt range");
+    static_assert(D <= 8, "at most 8 stages");
+    // one LDS object per stage, so that the compiler can tell a stage being
+    // read from the stages still being filled by direct loads
+    __shared__ half8 st0[STAGE], st1[STAGE], st2[STAGE], st3[STAGE];
+    __shared__ half8 st4[D > 4 ? STAGE : 1], st5[D > 5 ? STAGE : 1], st6[D > 6 ? STAGE : 1],
+        st7[D > 7 ? STAGE : 1];
+    auto stage_at = [&](auto slot_c) RPMI_INLINE -> half8* {
+        constexpr int k = decltype(slot_c)::value;
+        if constexpr (k == 0) return st0;
+        else if constexpr (k == 1) return st1;
+        else if constexpr (k == 2) return st2;
+        else if constexpr (k == 3) return st3;
+        else if constexpr (k == 4) return st4;
+        else if constexpr (k == 5) return st5;
+        else if constexpr (k == 6) return st6;
+        else return st7;
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int wm = wave % T::WM, wn = wave / T::WM;
     const int64_t bm = blockIdx.x, bn = blockIdx.y;
-    const int64_t nfull = p.n / T::BK;
+    const int kz = blockIdx.z;
 
-    // A: per-lane row pointer (its 16-byte column group folded in); per step a
-    // uniform contraction offset, advanced without divisions.
+    // this workgroup's share of the full contraction steps: [js, je)
+    const int64_t nfull = p.n / T::BK;
+    const int64_t nper = (nfull + p.ksplit - 1) / p.ksplit;
+    const int64_t js = kz * nper < nfull ? kz * nper : nfull;
+    const int64_t je = js + nper < nfull ? js + nper : nfull;
+    const int64_t nsteps = je - js;
+    const bool has_tail = kz == p.ksplit - 1 && nfull * T::BK < p.n;
+
+    // A: per-lane row pointer with its 16-byte column group folded in
     const char* abase[T::TM];
 #pragma unroll
     for (int tm = 0; tm < T::TM; ++tm) {
@@ -337,9 +373,16 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
         row = row < p.m ? row : p.m - 1;
         abase[tm] = reinterpret_cast<const char*>(p.A + row * p.s_row) + 16 * g;
     }
-    int64_t ioff = 0, irun = 0, iin = 0;       // element offset of the next step to issue
-    // Omega: per-thread byte offset of its chunks inside one step's block;
-    // the step's base address is uniform.
+    // Steps are issued in order from js; `jcur` is the step the next issue
+    // loads and irun + iin its contraction offset inside A's runs (advanced
+    // without divisions).  Issues past the last step of the share wrap back
+    // to js; their data lands in slots nobody reads.
+    const int64_t spr = p.k_inner / T::BK;                     // steps per contiguous run
+    int64_t jcur = js;
+    int64_t irun = nsteps > 0 ? (js / spr) * p.s_k_outer : 0;
+    int64_t iin = nsteps > 0 ? (js % spr) * T::BK : 0;
+    const int64_t irun0 = irun, iin0 = iin;
+    // Omega: per-thread byte offset of its chunks inside one step's block
     const char* ombase = static_cast<const char*>(p.omega);
     const int64_t ostep = (int64_t)T::KS * p.nt_count * 64 * 16;   // bytes per step
     uint32_t ovoff[CH];
@@ -350,29 +393,31 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
         ovoff[i] = (uint32_t)(((kbl * p.nt_count + bn * T::NTB + jn) * 64 + ql) * 16);
     }
 
-    floatx4 acc_hi[T::TM][T::TN], acc_lo[T::TM][T::TN];
+    // accumulators: with TWO_ACC, acc holds the hi products and acc2 the lo
+    // products (eq:shgemm-3 as written); otherwise one accumulator with the
+    // hi products taken against 2^11 Omega
+    floatx4 acc[T::TM][T::TN], acc2[TWO_ACC ? T::TM : 1][TWO_ACC ? T::TN : 1];
 #pragma unroll
     for (int tm = 0; tm < T::TM; ++tm)
 #pragma unroll
-        for (int j = 0; j < T::TN; ++j) {
-            acc_hi[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-            acc_lo[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int j = 0; j < T::TN; ++j) acc[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (TWO_ACC) {
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j) acc2[tm][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
     floatx4 ring[D][T::TM][T::KS][2];
     half8 hs[2][T::TM][T::KS], ls[2][T::TM][T::KS];   // split of the current / next step
 
-    // Issue step j (clamped to the last full step): Omega stage -> lds[slot]
-    // direct, then A -> ring[slot].
-    auto issue = [&](int64_t j, auto slot_c) RPMI_INLINE {
+    auto issue = [&](auto slot_c) RPMI_INLINE {
         constexpr int slot = decltype(slot_c)::value;
-        const bool real = j < nfull;
-        j = real ? j : nfull - 1;
-        const char* osrc = ombase + j * ostep;
+        const char* osrc = ombase + jcur * ostep;
 #pragma unroll
         for (int i = 0; i < CH; ++i)
             __builtin_amdgcn_global_load_lds(RPMI_GLB(osrc + ovoff[i]),
-                                             RPMI_LDS(&lds[slot][wave * 64 + i * T::THREADS]), 16, 0, 0);
-        const int64_t boff = ioff * 4;
+                                             RPMI_LDS(stage_at(slot_c) + wave * 64 + i * T::THREADS), 16, 0, 0);
+        const int64_t boff = (irun + iin) * 4;
 #pragma unroll
         for (int tm = 0; tm < T::TM; ++tm)
 #pragma unroll
@@ -381,13 +426,14 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
                 for (int h = 0; h < 2; ++h)
                     ring[slot][tm][kb][h] = *reinterpret_cast<const floatx4*>(
                         abase[tm] + boff + (kb * kKBlock + h * 16) * 4);
-        if (j + 1 < nfull) {
-            iin += T::BK;
-            const bool wrap = iin >= p.k_inner;
-            irun += wrap ? p.s_k_outer : 0;
-            iin = wrap ? 0 : iin;
-            ioff = irun + iin;
-        }
+        const bool last = jcur + 1 == je;
+        iin += T::BK;
+        const bool wrap = iin >= p.k_inner;
+        irun += wrap ? p.s_k_outer : 0;
+        iin = wrap ? 0 : iin;
+        irun = last ? irun0 : irun;
+        iin = last ? iin0 : iin;
+        jcur = last ? js : jcur + 1;
     };
 
     auto split_step = [&](const floatx4 (&a)[T::TM][T::KS][2], half8 (&h)[T::TM][T::KS],
@@ -398,65 +444,79 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
             for (int kb = 0; kb < T::KS; ++kb) split8(a[tm][kb][0], a[tm][kb][1], h[tm][kb], l[tm][kb]);
     };
 
+    // MFMAs of one step: fragments in groups of FG; per group the hi
+    // products (against 2^11 Omega) then the lo products, so the two updates
+    // of one accumulator are FG * TM instructions apart.
+    constexpr int FG = T::TN >= 4 ? 4 : T::TN;
+    static_assert(T::TN % FG == 0, "fragment groups");
     auto mfma_step = [&](const half8 (&h)[T::TM][T::KS], const half8 (&l)[T::TM][T::KS],
                          const half8* stage) RPMI_INLINE {
 #pragma unroll
-        for (int kb = 0; kb < T::KS; ++kb) {
-            half8 b[T::TN];
+        for (int kb = 0; kb < T::KS; ++kb)
 #pragma unroll
-            for (int j = 0; j < T::TN; ++j) b[j] = stage[(kb * T::NTB + wn * T::TN + j) * 64 + lane];
+            for (int j0 = 0; j0 < T::TN; j0 += FG) {
+                half8 b[FG];
 #pragma unroll
-            for (int j = 0; j < T::TN; ++j)
+                for (int f = 0; f < FG; ++f) b[f] = stage[(kb * T::NTB + wn * T::TN + j0 + f) * 64 + lane];
+                if constexpr (TWO_ACC) {
 #pragma unroll
-                for (int tm = 0; tm < T::TM; ++tm) {
-                    acc_hi[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(h[tm][kb], b[j], acc_hi[tm][j], 0, 0, 0);
-                    acc_lo[tm][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(l[tm][kb], b[j], acc_lo[tm][j], 0, 0, 0);
+                    for (int f = 0; f < FG; ++f)
+#pragma unroll
+                        for (int tm = 0; tm < T::TM; ++tm) {
+                            acc[tm][j0 + f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(h[tm][kb], b[f], acc[tm][j0 + f], 0, 0, 0);
+                            acc2[tm][j0 + f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(l[tm][kb], b[f], acc2[tm][j0 + f], 0, 0, 0);
+                        }
+                } else {
+#pragma unroll
+                    for (int f = 0; f < FG; ++f) {
+                        const half8 bs = scale_2p11(b[f]);
+#pragma unroll
+                        for (int tm = 0; tm < T::TM; ++tm)
+                            acc[tm][j0 + f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(h[tm][kb], bs, acc[tm][j0 + f], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int f = 0; f < FG; ++f)
+#pragma unroll
+                        for (int tm = 0; tm < T::TM; ++tm)
+                            acc[tm][j0 + f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(l[tm][kb], b[f], acc[tm][j0 + f], 0, 0, 0);
                 }
-        }
+            }
     };
 
-    // One pipelined step in slot s: wait + barrier, issue step it+D-1, then the
-    // MFMAs of step it (split already done) interleaved with the split of
-    // step it+1.  The wait and the barrier are one asm statement with a memory
-    // clobber so that no LDS access moves across.
-    auto step = [&](int64_t it, auto slot_c) RPMI_INLINE {
+    // One pipelined step in slot s: wait + barrier (at most D-3 later issues
+    // pending: this step's Omega stage and the next step's A have landed),
+    // issue, then this step's MFMAs interleaved with the split of the next.
+    auto step = [&](auto slot_c) RPMI_INLINE {
         constexpr int s = decltype(slot_c)::value;
         constexpr int cur = s & 1;
         wait_vm_barrier<(D - 3) * OPS>();
-        issue(it + D - 1, IntC<(s + D - 1) % D>{});
-        mfma_step(hs[cur], ls[cur], lds[s]);
+        issue(IntC<(s + D - 1) % D>{});
+        mfma_step(hs[cur], ls[cur], stage_at(slot_c));
         split_step(ring[(s + 1) % D], hs[cur ^ 1], ls[cur ^ 1]);
-        // interleave: Omega fragment reads up front, then one MFMA per
-        // group of split instructions
         __builtin_amdgcn_sched_group_barrier(kSchedVmemRead, OPS, 0);
-        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, T::TN, 0);
 #pragma unroll
         for (int q = 0; q < 2 * T::TM * T::TN * T::KS; ++q) {
+            if (q % (2 * FG * T::TM) == 0) __builtin_amdgcn_sched_group_barrier(kSchedDsRead, FG, 0);
             __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
             __builtin_amdgcn_sched_group_barrier(kSchedValu, 2, 0);
-            if (q == T::TM * T::TN) __builtin_amdgcn_sched_group_barrier(kSchedDsRead, T::TN, 0);
         }
     };
 
-    if (nfull > 0) {
-        static_for<D - 1>([&](auto sc) RPMI_INLINE { issue(decltype(sc)::value, sc); });
-        // A of step 0 is followed by D-2 issues
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_waitcnt(VmCnt<(D - 2) * OPS>::value);
+    if (nsteps > 0) {
+        static_for<D - 1>([&](auto sc) RPMI_INLINE { issue(sc); });
+        wait_vm_barrier<(D - 2) * OPS>();       // A of the first step (no LDS read yet)
         split_step(ring[0], hs[0], ls[0]);
-        const int64_t ngroups = nfull / D;
-        for (int64_t grp = 0; grp < ngroups; ++grp) {
-            const int64_t it0 = grp * D;
-            static_for<D>([&](auto sc) RPMI_INLINE { step(it0 + decltype(sc)::value, sc); });
-        }
-        const int64_t it0 = ngroups * D;
+        const int64_t ngroups = nsteps / D;
+        for (int64_t grp = 0; grp < ngroups; ++grp)
+            static_for<D>([&](auto sc) RPMI_INLINE { step(sc); });
+        const int64_t rem = nsteps - ngroups * D;
         static_for<D>([&](auto sc) RPMI_INLINE {
-            if (it0 + decltype(sc)::value < nfull) step(it0 + decltype(sc)::value, sc);
+            if (decltype(sc)::value < rem) step(sc);
         });
         wait_vm_barrier<0>();
     }
 
-    if (nfull * T::BK < p.n) {   // contraction tail: guarded loads, zero-padded Omega rows
+    if (has_tail) {   // contraction tail: guarded loads, zero-padded Omega rows
         const AStream<T, true> as = make_astream<T, true>(p, bm, wm, c, g);
         floatx4 a[T::TM][T::KS][2];
         const int64_t k0 = nfull * T::BK;
@@ -466,14 +526,52 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
         for (int i = 0; i < CH; ++i) {
             const int q = tid + i * T::THREADS;
             const int kbl = q / (T::NTB * 64), jn = (q / 64) % T::NTB, ql = q % 64;
-            lds[0][q] = om[((nfull * T::KS + kbl) * p.nt_count + bn * T::NTB + jn) * 64 + ql];
+            st0[q] = om[((nfull * T::KS + kbl) * p.nt_count + bn * T::NTB + jn) * 64 + ql];
         }
         __syncthreads();
         split_step(a, hs[0], ls[0]);
-        mfma_step(hs[0], ls[0], lds[0]);
+        mfma_step(hs[0], ls[0], st0);
     }
 
-    if (any_nonfinite(acc_lo)) atomicOr(p.status, kStatusRange);
+    if constexpr (TWO_ACC) {
+        // acc <- 2^11 acc_hi + acc_lo: the epilogue then scales by 2^-11 as in
+        // the single-accumulator form (the 2^11 scaling is exact)
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j) acc[tm][j] = acc[tm][j] * 2048.0f + acc2[tm][j];
+    }
+    if (any_nonfinite(acc)) atomicOr(p.status, kStatusRange);
+
+    if (p.ksplit > 1) {
+        // partial sums in lane order (16 bytes per lane per fragment), then the
+        // last workgroup of the tile adds all ksplit partials in order z = 0, 1, ...
+        const int64_t tile = bm * gridDim.y + bn;
+        constexpr int TILE_F4 = T::TM * T::TN * T::THREADS;      // float4s per partial tile
+        floatx4* mine = reinterpret_cast<floatx4*>(p.partial) + (tile * p.ksplit + kz) * TILE_F4;
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j) mine[(tm * T::TN + j) * T::THREADS + tid] = acc[tm][j];
+        __threadfence();
+        __shared__ unsigned int arrival;
+        __syncthreads();
+        if (tid == 0) arrival = atomicAdd(&p.counters[tile], 1u);
+        __syncthreads();
+        if (arrival != (unsigned)p.ksplit - 1) return;
+        __threadfence();
+        const floatx4* all = reinterpret_cast<const floatx4*>(p.partial) + tile * p.ksplit * TILE_F4;
+#pragma unroll
+        for (int tm = 0; tm < T::TM; ++tm)
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j) {
+                floatx4 sum = __builtin_nontemporal_load(&all[(tm * T::TN + j) * T::THREADS + tid]);
+                for (int z = 1; z < p.ksplit; ++z)
+                    sum += __builtin_nontemporal_load(&all[(z * TILE_F4) + (tm * T::TN + j) * T::THREADS + tid]);
+                acc[tm][j] = sum;
+            }
+        if (tid == 0) p.counters[tile] = 0;   // ready for the next launch
+    }
 
 #pragma unroll
     for (int tm = 0; tm < T::TM; ++tm)
@@ -484,7 +582,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
             for (int e = 0; e < 4; ++e) {
                 const int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + 4 * g + e;
                 if (row < p.m && col < p.r)
-                    p.Y[row * p.ldy + col] = acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f;
+                    p.Y[row * p.ldy + col] = acc[tm][j][e] * 0x1p-11f;
             }
         }
 }
@@ -624,15 +722,37 @@ int small_grid(int64_t total) {
 
 int64_t split_f16_col_block() { return SplitTile::BN; }
 int64_t f32_col_block() { return F32Tile::BN; }
-int64_t proj_k_block() { return SplitTile::BK > F32Tile::BK ? SplitTile::BK : F32Tile::BK; }
+int64_t proj_k_block() { return 64; }   // multiple of every tile's step (SplitTile 64, DmaTile 32, F32Tile 32)
+static_assert(64 % SplitTile::BK == 0 && 64 % DmaTile::BK == 0 && 64 % F32Tile::BK == 0, "k block");
+static_assert(SplitTile::BN == DmaTile::BN, "both split paths read the same packed Omega");
+
+SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
+    using T = DmaTile;
+    SplitPlan plan{1, 0, 0};
+    const int64_t tiles = ((m + T::BM - 1) / T::BM) * ((r + T::BN - 1) / T::BN);
+    const int64_t nfull = n / T::BK;
+    if (tiles <= 0 || nfull <= 0) return plan;
+    int64_t k = num_cus / tiles;                 // fill the chip with tiles x k workgroups
+    k = k > 16 ? 16 : k;
+    k = k > nfull / (2 * kDmaDepth) ? nfull / (2 * kDmaDepth) : k;   // keep shares >= 2 groups
+    if (k < 2) return plan;
+    plan.ksplit = (int)k;
+    plan.partial_bytes = (size_t)tiles * k * T::BM * T::BN * sizeof(float);
+    plan.counter_bytes = (size_t)tiles * sizeof(unsigned int);
+    return plan;
+}
 
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
-    using T = SplitTile;
-    dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN));
-    if (vector_ok(a))
-        hipLaunchKernelGGL((project_split_f16_dma_kernel<T, kSplitDepth>), grid, dim3(T::THREADS), 0, s, a);
-    else
+    if (vector_ok(a)) {
+        using T = DmaTile;
+        dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN),
+                  (unsigned)(a.ksplit > 1 ? a.ksplit : 1));
+        hipLaunchKernelGGL((project_split_f16_dma_kernel<T, kDmaDepth, kDmaTwoAcc>), grid, dim3(T::THREADS), 0, s, a);
+    } else {
+        using T = SplitTile;
+        dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN));
         hipLaunchKernelGGL((project_split_f16_kernel<T, kSplitDepth, false>), grid, dim3(T::THREADS), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -20,6 +20,11 @@ struct rp_ctx_s {
     unsigned int* d_status = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // contraction-split workspace of the split-FP16 projection: per-tile
+    // counters (kept zero between launches) followed by partial sums
+    void* split_ws = nullptr;
+    size_t split_ws_bytes = 0;
+    int num_cus = 0;
     std::string last_error;
 };
 
@@ -131,6 +136,10 @@ rp_status rp_create(rp_ctx* out, int device) {
     if (!ctx) return fail(nullptr, RP_ERR_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->table_count = n;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+    }
     auto cleanup = [&](hipError_t err, const char* what) {
         rp_status s = hip_fail(nullptr, err, what);
         rp_destroy(ctx);
@@ -156,6 +165,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->d_guide) (void)hipFree(ctx->d_guide);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->split_ws) (void)hipFree(ctx->split_ws);
     delete ctx;
     return RP_OK;
 }
@@ -257,6 +267,24 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
     return RP_OK;
 }
 
+// Grow the split workspace to hold `counters` zeroed counter bytes plus
+// `partials` bytes (synchronises the device when it grows).
+rp_status ensure_split_workspace(rp_ctx ctx, size_t counters, size_t partials) {
+    const size_t need = ((counters + 255) & ~size_t(255)) + partials;
+    if (need <= ctx->split_ws_bytes) return RP_OK;
+    RP_HIP(ctx, hipDeviceSynchronize());
+    if (ctx->split_ws) {
+        RP_HIP(ctx, hipFree(ctx->split_ws));
+        ctx->split_ws = nullptr;
+        ctx->split_ws_bytes = 0;
+    }
+    const size_t bytes = (need + 0xFFFFF) & ~size_t(0xFFFFF);
+    RP_HIP(ctx, hipMalloc(&ctx->split_ws, bytes));
+    RP_HIP(ctx, hipMemset(ctx->split_ws, 0, bytes));
+    ctx->split_ws_bytes = bytes;
+    return RP_OK;
+}
+
 rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi::PackedOmega& pk,
                             rp_algo_t algo, float* Y, int64_t ldy, hipStream_t s) {
     rpmi::ProjArgs a;
@@ -267,8 +295,21 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
     a.omega = pk.data; a.nt_count = pk.nt_count;
     a.Y = Y; a.ldy = ldy; a.r = r;
     a.status = ctx->d_status;
-    if (algo == RP_ALGO_SPLIT_F16) RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
-    else RP_HIP(ctx, rpmi::launch_project_f32(a, s));
+    a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+    if (algo == RP_ALGO_SPLIT_F16) {
+        const rpmi::SplitPlan plan = rpmi::plan_split_f16(a.m, a.n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
+        if (plan.ksplit > 1) {
+            rp_status st = ensure_split_workspace(ctx, plan.counter_bytes, plan.partial_bytes);
+            if (st != RP_OK) return st;
+            a.ksplit = plan.ksplit;
+            a.counters = static_cast<unsigned int*>(ctx->split_ws);
+            a.partial = reinterpret_cast<float*>(static_cast<char*>(ctx->split_ws) +
+                                                 ((plan.counter_bytes + 255) & ~size_t(255)));
+        }
+        RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
+    } else {
+        RP_HIP(ctx, rpmi::launch_project_f32(a, s));
+    }
     return RP_OK;
 }
 

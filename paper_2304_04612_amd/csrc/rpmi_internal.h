@@ -46,7 +46,22 @@ struct ProjArgs {
     float* Y;
     int64_t ldy, r;
     unsigned int* status;             // device status word
+    // contraction split (split-FP16 path): ksplit workgroups share one output
+    // tile; each writes its partial sums to `partial`, the last one to finish
+    // (per-tile counter) adds them in a fixed order and writes Y
+    int ksplit;
+    float* partial;                   // ksplit * tiles * BM * BN floats
+    unsigned int* counters;           // one per output tile, zero between launches
 };
+
+// Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
+// contraction split it will use; the counters must be zero initially.
+struct SplitPlan {
+    int ksplit;
+    size_t partial_bytes;
+    size_t counter_bytes;
+};
+SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus);
 
 constexpr unsigned int kStatusRange = 1u;
 constexpr unsigned int kStatusNotSpd = 2u;
