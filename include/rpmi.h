@@ -174,6 +174,33 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
                             rp_algo_t algo, float* Y, int64_t ldy, void* stream);
 
 /*
+ * Randomized SVD (Algorithm 1, Sec. 2.2) of the m x n FP32 matrix A (row-major,
+ * leading dimension lda >= n), with target rank k and oversampling s
+ * (p = k + s columns of Omega, 1 <= k <= p <= min(m, n), p <= 1024) and
+ * power_iters steps of the power scheme (Sec. 2.1), re-orthonormalised at
+ * every half step:
+ *     Y = A Omega;  repeat q times { Q = QR(Y); W = QR(A^T Q); Y = A W };
+ *     Q = QR(Y);  B = Q^T A;  U', S, V' = SVD(B);  U = Q U'[:, :k].
+ * Omega is generated from (seed, stream_id 0) in omega_type and the
+ * projection runs with `algo` (RP_ALGO_SPLIT_F16 is the paper's method;
+ * RP_ALGO_F32 the baseline); the other products are FP32 with FP64
+ * accumulation.  Every QR is CholeskyQR2 with the Gram matrix, Cholesky
+ * factor and triangular inverse in FP64; the SVD of B is taken as
+ * B^T = Q_B R_B (CholeskyQR2) followed by a one-sided Jacobi SVD of R_B^T in
+ * FP64.
+ * Outputs (device): U m x k (ldu >= k), S k doubles in descending order, VT
+ * k x n (ldvt >= n).  Singular vectors are determined up to sign.
+ * Device conditions: RP_ERR_NOT_SPD (a Cholesky pivot was not positive:
+ * Y numerically rank-deficient beyond FP64 Gram range), RP_ERR_NOT_CONVERGED
+ * (Jacobi), RP_ERR_RANGE (split path, A outside FP16 range).  Allocates or
+ * grows the context workspace as needed (synchronising the device then).
+ */
+rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
+               int64_t k, int64_t oversample, int32_t power_iters,
+               uint64_t seed, rp_omega_t omega_type, rp_algo_t algo,
+               float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* stream);
+
+/*
  * Split of an FP32 array into FP16 hi and lo (Sec. 4.1, eq:shgemm-1/2), as the
  * projection performs it in registers: hi = RN16(a), lo = RN16((a - hi) 2^11).
  * Exposed so that the split can be checked bit for bit.  x: count floats;

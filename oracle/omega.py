@@ -25,8 +25,10 @@ import numpy as np
 from . import lattice, philox
 
 
-def _words(seed, stream_id, n, r, c3):
-    i = np.arange(n, dtype=np.uint64)[:, None]
+def _words(seed, stream_id, n, r, c3, rows=None):
+    i = (np.arange(n, dtype=np.uint64) if rows is None
+         else np.asarray(rows, dtype=np.uint64))[:, None]
+    n = i.shape[0]
     jb = (np.arange(r, dtype=np.uint64) >> np.uint64(2))[None, :]
     x0, x1, x2, x3 = philox.philox4x64_10(i, jb, np.uint64(stream_id), np.uint64(c3),
                                           np.uint64(seed), np.uint64(0))
@@ -35,16 +37,17 @@ def _words(seed, stream_id, n, r, c3):
     return np.take_along_axis(stack, np.broadcast_to(w, (1, n, r)), axis=0)[0]
 
 
-def _cell_and_sign(seed, stream_id, n, r):
-    x = _words(seed, stream_id, n, r, 0)
+def _cell_and_sign(seed, stream_id, n, r, rows=None):
+    x = _words(seed, stream_id, n, r, 0, rows)
     sign = (x & np.uint64(1)).astype(np.uint16)
     k = lattice.cell_index(x >> np.uint64(1))
     return k, sign
 
 
-def omega_f16_bits(seed, stream_id, n, r):
-    """FP16 bit patterns (uint16, n x r) of Omega."""
-    k, sign = _cell_and_sign(seed, stream_id, n, r)
+def omega_f16_bits(seed, stream_id, n, r, rows=None):
+    """FP16 bit patterns (uint16, n x r) of Omega; with ``rows`` given, only
+    those rows (any indices, n ignored)."""
+    k, sign = _cell_and_sign(seed, stream_id, n, r, rows)
     bits = k.astype(np.uint16) | (sign << np.uint16(15))
     return np.where(k == 0, np.uint16(0), bits).astype(np.uint16)
 

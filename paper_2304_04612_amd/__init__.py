@@ -66,6 +66,7 @@ def lib():
         "rp_omega_pack": [vp, u64, u32, vp, i64, i32, i64, i64, i32, vp, vp],
         "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, vp, i64, vp],
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
+        "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, vp, i64, vp, vp, i64, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -215,6 +216,24 @@ def rp_split_f16(x, ctx=None):
     lo = torch.empty(x.shape, dtype=torch.int16, device=x.device)
     _check(ctx.handle, lib().rp_split_f16(ctx.handle, _ptr(x), x.numel(), _ptr(hi), _ptr(lo), _stream()))
     return hi, lo
+
+
+def rsvd(a, k, oversample=10, power_iters=0, seed=0, omega_type="f16", algo="split_f16", ctx=None):
+    """Randomized SVD (Algorithm 1) of the float32 CUDA matrix ``a`` (m x n).
+    Returns (U m x k float32, S k float64, VT k x n float32)."""
+    import torch
+    ctx = ctx or default_context()
+    if a.dtype != torch.float32 or not a.is_cuda or a.dim() != 2 or a.stride(1) != 1:
+        raise TypeError("a must be a 2-D float32 CUDA tensor with unit column stride")
+    m, n = a.shape
+    dev = f"cuda:{ctx.device}"
+    u = torch.empty((m, k), dtype=torch.float32, device=dev)
+    sv = torch.empty((k,), dtype=torch.float64, device=dev)
+    vt = torch.empty((k, n), dtype=torch.float32, device=dev)
+    _check(ctx.handle, lib().rsvd(ctx.handle, m, n, _ptr(a), a.stride(0), k, oversample, power_iters, seed,
+                                  OMEGA_TYPES[omega_type], ALGOS[algo], _ptr(u), u.stride(0), _ptr(sv),
+                                  _ptr(vt), vt.stride(0), _stream()))
+    return u, sv, vt
 
 
 def rp_get_device_status(clear=True, ctx=None):

@@ -1,0 +1,435 @@
+// Dense FP64 building blocks for the randomized SVD (Algorithm 1) around the
+// projection: CholeskyQR2 (Gram matrix, Cholesky, triangular inverse, Q =
+// Y R^-1) and the small SVD (one-sided Jacobi).  The paper uses cuSOLVER for
+// these steps (Sec. 5.1); here they are hand-written HIP kernels, FP64
+// throughout (the Gram of the skinny Y is formed in FP64 from FP32 data).
+//
+// * gemm_acc64: C = alpha * op(A) op(B) (+ beta C) with arbitrary row/column
+//   strides for every operand, FP64 accumulation, 64x64 output tiles staged
+//   through LDS in 16-deep slices; deterministic (fixed summation order).
+// * Cholesky (lower, in place): blocked right-looking, 64-wide blocks: the
+//   diagonal block is factored in LDS by one workgroup, the panel below is
+//   solved against it, the trailing matrix is updated with gemm_acc64.  A
+//   non-positive pivot sets the NOT_SPD status bit and the factorization
+//   continues on |pivot| so that every kernel still completes.
+// * Inverse of a lower-triangular L: blocked; diagonal blocks inverted in LDS,
+//   off-diagonal blocks X_ij = -X_ii (sum_{j<=l<i} L_il X_lj) row block by row
+//   block with gemm_acc64.
+// * One-sided Jacobi SVD of a small square matrix in one workgroup
+//   (round-robin pair ordering, rotation angles from the 2x2 Gram of each
+//   column pair, de Rijk's convergence test on the relative off-diagonal).
+#include "rpmi_internal.h"
+
+namespace rpmi {
+namespace {
+
+constexpr int GT = 64;      // output tile
+constexpr int GK = 16;      // contraction slice
+constexpr int NB = 64;      // block size of the factorizations
+
+template <class T>
+__device__ __forceinline__ double ld(const T* p) { return (double)*p; }
+
+// C[i][j] = alpha * sum_k A(i,k) B(k,j) + beta * C[i][j], A(i,k) = a[i*sam + k*sak],
+// B(k,j) = b[k*sbk + j*sbn], C[i][j] = c[i*scm + j*scn].  beta == 0 ignores C's
+// old contents (NaN included).  256 threads, each owning a 4x4 block of the
+// 64x64 tile.
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(256) void gemm_acc64_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ a, int64_t sam, int64_t sak,
+    const TB* __restrict__ b, int64_t sbk, int64_t sbn, double beta, TC* __restrict__ c, int64_t scm,
+    int64_t scn) {
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;       // 16 x 16 threads, 4x4 each
+    const int64_t i0 = blockIdx.y * (int64_t)GT, j0 = blockIdx.x * (int64_t)GT;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < K; k0 += GK) {
+        // stage 64x16 of A and 16x64 of B (4 elements per thread each)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;          // 0..1023
+            // A: pick the mapping whose fastest index follows the unit stride
+            int ii, kk;
+            if (sak == 1) { kk = e % GK; ii = e / GK; } else { ii = e % GT; kk = e / GT; }
+            const int64_t gi = i0 + ii, gk = k0 + kk;
+            As[kk][ii] = (gi < M && gk < K) ? ld(a + gi * sam + gk * sak) : 0.0;
+            int jj, kb;
+            if (sbn == 1) { jj = e % GT; kb = e / GT; } else { kb = e % GK; jj = e / GK; }
+            const int64_t gj = j0 + jj, gkb = k0 + kb;
+            Bs[kb][jj] = (gj < N && gkb < K) ? ld(b + gkb * sbk + gj * sbn) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { av[u] = As[kk][ty + 16 * u]; bv[u] = Bs[kk][tx + 16 * u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
+            if (gi < M && gj < N) {
+                TC* dst = c + gi * scm + gj * scn;
+                const double old = beta != 0.0 ? (double)*dst : 0.0;
+                *dst = (TC)(alpha * acc[u][v] + beta * old);
+            }
+        }
+}
+
+// ---------------------------------------------------------------- Cholesky
+// Factor the nb x nb diagonal block at (k, k) in place (lower), in LDS.
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int64_t lda, int64_t k, int nb,
+                                                         unsigned int* status) {
+    __shared__ double T[NB][NB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += 256) T[e / nb][e % nb] = A[(k + e / nb) * lda + k + e % nb];
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        __shared__ double d;
+        if (tid == 0) {
+            double v = T[j][j];
+            if (!(v > 0.0)) {             // breakdown (or NaN): record, keep going
+                atomicOr(status, kStatusNotSpd);
+                v = fabs(v) > 0.0 ? fabs(v) : 1.0;
+            }
+            d = sqrt(v);
+            T[j][j] = d;
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < nb; i += 256) T[i][j] /= d;
+        __syncthreads();
+        for (int e = tid; e < (nb - j - 1) * (nb - j - 1); e += 256) {
+            const int i = j + 1 + e / (nb - j - 1), l = j + 1 + e % (nb - j - 1);
+            if (l <= i) T[i][l] -= T[i][j] * T[l][j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, l = e % nb;
+        A[(k + i) * lda + k + l] = l <= i ? T[i][l] : 0.0;
+    }
+}
+
+// Rows [k+nb, p) of block column k: X <- X L_kk^-T (row by row forward
+// substitution; one workgroup per 64 rows, L_kk in LDS).
+__global__ __launch_bounds__(256) void trsm_panel_kernel(double* A, int64_t lda, int64_t k, int nb,
+                                                         int64_t p) {
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[64][NB + 1];
+    const int tid = threadIdx.x;
+    const int64_t r0 = k + nb + blockIdx.x * 64;
+    const int rows = (int)(p - r0 < 64 ? p - r0 : 64);
+    for (int e = tid; e < nb * nb; e += 256) L[e / nb][e % nb] = A[(k + e / nb) * lda + k + e % nb];
+    for (int e = tid; e < rows * nb; e += 256) X[e / nb][e % nb] = A[(r0 + e / nb) * lda + k + e % nb];
+    __syncthreads();
+    // x_j = (x_j - sum_{l<j} x_l L[j][l]) / L[j][j], for each row independently
+    if (tid < rows) {
+        for (int j = 0; j < nb; ++j) {
+            double s = X[tid][j];
+            for (int l = 0; l < j; ++l) s -= X[tid][l] * L[j][l];
+            X[tid][j] = s / L[j][j];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * nb; e += 256) A[(r0 + e / nb) * lda + k + e % nb] = X[e / nb][e % nb];
+}
+
+// ------------------------------------------------------- triangular inverse
+// Invert each nb x nb diagonal block of lower-triangular L into X (one
+// workgroup per block; column-wise forward substitution in LDS).
+__global__ __launch_bounds__(256) void trtri_diag_kernel(const double* L, int64_t ldl, double* X,
+                                                         int64_t ldx, int64_t p) {
+    __shared__ double T[NB][NB + 1];
+    __shared__ double V[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const int64_t k = blockIdx.x * (int64_t)NB;
+    const int nb = (int)(p - k < NB ? p - k : NB);
+    for (int e = tid; e < nb * nb; e += 256) {
+        T[e / nb][e % nb] = L[(k + e / nb) * ldl + k + e % nb];
+        V[e / nb][e % nb] = 0.0;
+    }
+    __syncthreads();
+    // column c of the inverse solves T v = e_c
+    if (tid < nb) {
+        const int cidx = tid;
+        for (int i = cidx; i < nb; ++i) {
+            double s = i == cidx ? 1.0 : 0.0;
+            for (int l = cidx; l < i; ++l) s -= T[i][l] * V[l][cidx];
+            V[i][cidx] = s / T[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += 256) X[(k + e / nb) * ldx + k + e % nb] = V[e / nb][e % nb];
+}
+
+// Block row i of the inverse: X[i, 0:r0] currently holds T = L[i, 0:r0]
+// X[0:r0, 0:r0]; replace it by -X_ii T.  One workgroup per 64-column chunk;
+// X_ii and the chunk of T are staged in LDS.
+__global__ __launch_bounds__(256) void trtri_apply_diag_kernel(double* X, int64_t ldx, int64_t r0, int rows) {
+    __shared__ double D[NB][NB + 1];
+    __shared__ double T[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const int64_t c0 = blockIdx.x * (int64_t)NB;
+    const int cols = (int)(r0 - c0 < NB ? r0 - c0 : NB);
+    for (int e = tid; e < rows * rows; e += 256) D[e / rows][e % rows] = X[(r0 + e / rows) * ldx + r0 + e % rows];
+    for (int e = tid; e < rows * cols; e += 256) T[e / cols][e % cols] = X[(r0 + e / cols) * ldx + c0 + e % cols];
+    __syncthreads();
+    for (int e = tid; e < rows * cols; e += 256) {
+        const int i = e / cols, j = e % cols;
+        double acc = 0.0;
+        for (int l = 0; l <= i; ++l) acc += D[i][l] * T[l][j];
+        X[(r0 + i) * ldx + c0 + j] = -acc;
+    }
+}
+
+// Zero the strictly upper part of a p x p matrix (so that it is exactly lower).
+__global__ void zero_upper_kernel(double* A, int64_t lda, int64_t p) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < p * p; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / p, j = e % p;
+        if (j > i) A[i * lda + j] = 0.0;
+    }
+}
+
+// ----------------------------------------------------------------- Jacobi SVD
+// One-sided Jacobi on the columns of W (n x n, FP64, row-major, ld = n) in one
+// workgroup; V (n x n) accumulates the rotations.  On return the columns of W
+// are mutually orthogonal: W_in V = W_out.  Converged when every pair
+// satisfies |w_i . w_j| <= tol sqrt(|w_i|^2 |w_j|^2); sets NOT_CONVERGED after
+// max_sweeps otherwise.
+__global__ __launch_bounds__(1024) void jacobi_svd_kernel(double* W, double* V, int n, int max_sweeps,
+                                                          double tol, unsigned int* status) {
+    const int tid = threadIdx.x;
+    __shared__ int rotated;
+    __shared__ int perm[1025];
+    for (int e = tid; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    const int m = n + (n & 1);                 // even count for round-robin (a dummy if odd)
+    for (int i = tid; i < m; i += blockDim.x) perm[i] = i;
+    __syncthreads();
+    const int pairs = m / 2;
+    // threads per pair: a power of two <= blockDim / pairs (>= 1)
+    int tpp = 1;
+    while (tpp * 2 * pairs <= (int)blockDim.x && tpp < 64) tpp *= 2;
+    const int pair = tid / tpp, sub = tid % tpp;
+    bool converged = false;
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < m - 1; ++round) {
+            for (int pr = pair; pr < pairs; pr += blockDim.x / tpp) {
+                int a = perm[pr], bb = perm[m - 1 - pr];
+                if (a > bb) { const int t = a; a = bb; bb = t; }
+                const bool live = bb < n && pr < pairs;
+                double alpha = 0.0, beta = 0.0, gamma = 0.0;
+                if (live) {
+                    for (int r = sub; r < n; r += tpp) {
+                        const double x = W[r * n + a], y = W[r * n + bb];
+                        alpha += x * x; beta += y * y; gamma += x * y;
+                    }
+                }
+                // reduce within the tpp lanes of this pair (contiguous lanes)
+                for (int off = tpp / 2; off > 0; off /= 2) {
+                    alpha += __shfl_xor(alpha, off, tpp);
+                    beta += __shfl_xor(beta, off, tpp);
+                    gamma += __shfl_xor(gamma, off, tpp);
+                }
+                if (live && fabs(gamma) > tol * sqrt(alpha * beta) && gamma != 0.0) {
+                    // rotation zeroing the (a, bb) entry of the 2x2 Gram
+                    const double zeta = (beta - alpha) / (2.0 * gamma);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                    for (int r = sub; r < n; r += tpp) {
+                        const double x = W[r * n + a], y = W[r * n + bb];
+                        W[r * n + a] = cs * x - sn * y;
+                        W[r * n + bb] = sn * x + cs * y;
+                        const double vx = V[r * n + a], vy = V[r * n + bb];
+                        V[r * n + a] = cs * vx - sn * vy;
+                        V[r * n + bb] = sn * vx + cs * vy;
+                    }
+                    if (sub == 0) rotated = 1;
+                }
+            }
+            __syncthreads();
+            // round-robin: keep position 0, rotate the rest
+            if (tid == 0) {
+                const int last = perm[m - 1];
+                for (int i = m - 1; i > 1; --i) perm[i] = perm[i - 1];
+                perm[1] = last;
+            }
+            __syncthreads();
+        }
+        converged = rotated == 0;
+        __syncthreads();
+    }
+    if (!converged && tid == 0) atomicOr(status, kStatusNotConverged);
+}
+
+// sigma_j = |w_j|; rank the columns by sigma descending (ties by index); write
+// sigma in that order and the permutation (one workgroup, n <= 1024).
+__global__ __launch_bounds__(1024) void svd_finish_kernel(const double* W, int n, double* sig_sorted,
+                                                          int* order) {
+    __shared__ double s[1024];
+    const int tid = threadIdx.x;
+    for (int j = tid; j < n; j += blockDim.x) {
+        double a = 0.0;
+        for (int r = 0; r < n; ++r) a += W[r * n + j] * W[r * n + j];
+        s[j] = sqrt(a);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        int rank = 0;
+        for (int i = 0; i < n; ++i) rank += (s[i] > s[j]) || (s[i] == s[j] && i < j);
+        sig_sorted[rank] = s[j];
+        order[rank] = j;
+    }
+}
+
+// U_r[:, c] = W[:, order[c]] / sigma_c (0 column when sigma_c == 0), V_r
+// columns gathered in the same order; both n x ncols, row-major, FP64.
+__global__ void svd_gather_kernel(const double* W, const double* Vin, int n, const double* sig,
+                                  const int* order, int ncols, double* Ur, double* Vr) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * ncols;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ncols), cidx = (int)(e % ncols);
+        const int src = order[cidx];
+        const double sg = sig[cidx];
+        Ur[e] = sg > 0.0 ? W[(int64_t)r * n + src] / sg : 0.0;
+        Vr[e] = Vin[(int64_t)r * n + src];
+    }
+}
+
+__global__ void convert_f64_f32_kernel(const double* x, float* y, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+int grid1d(int64_t total, int block = 256) {
+    int64_t g = (total + block - 1) / block;
+    return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                      const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
+                      hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
+    hipLaunchKernelGGL((gemm_acc64_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M, N, K, alpha, a, sam, sak, b,
+                       sbk, sbn, beta, c, scm, scn);
+    return hipGetLastError();
+}
+
+template hipError_t gemm_acc64<float, float, double>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                     int64_t, const float*, int64_t, int64_t, double, double*,
+                                                     int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64<double, double, double>(int64_t, int64_t, int64_t, double, const double*,
+                                                       int64_t, int64_t, const double*, int64_t, int64_t,
+                                                       double, double*, int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64<float, double, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                     int64_t, const double*, int64_t, int64_t, double, float*,
+                                                     int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64<double, double, float>(int64_t, int64_t, int64_t, double, const double*,
+                                                      int64_t, int64_t, const double*, int64_t, int64_t,
+                                                      double, float*, int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64<float, double, double>(int64_t, int64_t, int64_t, double, const float*,
+                                                      int64_t, int64_t, const double*, int64_t, int64_t,
+                                                      double, double*, int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                    int64_t, const float*, int64_t, int64_t, double, float*,
+                                                    int64_t, int64_t, hipStream_t);
+
+hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s) {
+    hipLaunchKernelGGL(trtri_apply_diag_kernel, dim3((unsigned)((r0 + NB - 1) / NB)), dim3(256), 0, s, X, ldx, r0,
+                       (int)rows);
+    return hipGetLastError();
+}
+
+hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, unsigned int* status,
+                      hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, W, V, n, max_sweeps, tol, status);
+    return hipGetLastError();
+}
+
+hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
+                      double* Vr, hipStream_t s) {
+    hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(1024), 0, s, W, n, sig, order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(svd_gather_kernel, dim3(grid1d((int64_t)n * ncols)), dim3(256), 0, s, W, V, n, sig, order,
+                       ncols, Ur, Vr);
+    return hipGetLastError();
+}
+
+hipError_t convert_f64_f32(const double* x, float* y, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(convert_f64_f32_kernel, dim3(grid1d(count)), dim3(256), 0, s, x, y, count);
+    return hipGetLastError();
+}
+
+hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_zero_upper(A, lda, p, s)) != hipSuccess) return e;
+    for (int64_t k = 0; k < p; k += NB) {
+        const int nb = (int)(p - k < NB ? p - k : NB);
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, A, lda, k, nb, status);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t below = p - k - nb;
+        if (below <= 0) break;
+        hipLaunchKernelGGL(trsm_panel_kernel, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, s, A, lda, k,
+                           nb, p);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // trailing update: A22 -= L21 L21^T (full square; the upper part is
+        // cleared again at the end)
+        double* L21 = A + (k + nb) * lda + k;
+        double* A22 = A + (k + nb) * lda + k + nb;
+        if ((e = gemm_acc64<double, double, double>(below, below, nb, -1.0, L21, lda, 1, L21, 1, lda, 1.0, A22,
+                                                    lda, 1, s)) != hipSuccess)
+            return e;
+    }
+    return launch_zero_upper(A, lda, p, s);
+}
+
+hipError_t launch_zero_upper(double* A, int64_t lda, int64_t p, hipStream_t s) {
+    if (p <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(grid1d(p * p)), dim3(256), 0, s, A, lda, p);
+    return hipGetLastError();
+}
+
+hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t p, hipStream_t s) {
+    hipError_t e;
+    const int64_t nblk = (p + NB - 1) / NB;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(grid1d(p * p)), dim3(256), 0, s, X, ldx, p);   // upper = 0
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(trtri_diag_kernel, dim3((unsigned)nblk), dim3(256), 0, s, L, ldl, X, ldx, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // block row i (i >= 1): X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i]); the
+    // product T is written into block row i of X itself (those entries are
+    // not read by it), then replaced by -X_ii T
+    for (int64_t i = 1; i < nblk; ++i) {
+        const int64_t r0 = i * NB;
+        const int64_t rows = p - r0 < NB ? p - r0 : NB;
+        double* Xi = X + r0 * ldx;                   // block row i, columns 0:r0
+        // T = L[r0:r0+rows, 0:r0] X[0:r0, 0:r0]
+        if ((e = gemm_acc64<double, double, double>(rows, r0, r0, 1.0, L + r0 * ldl, ldl, 1, X, ldx, 1, 0.0, Xi,
+                                                    ldx, 1, s)) != hipSuccess)
+            return e;
+        // X[i, 0:i] = -X_ii T (in place, chunk by chunk in LDS)
+        if ((e = launch_trtri_apply_diag(X, ldx, r0, rows, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace rpmi

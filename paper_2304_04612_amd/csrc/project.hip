@@ -41,9 +41,11 @@ struct Tile {
 };
 
 using SplitTile = Tile<2, 2, 2, 8, 2>;   // general split path: 64 x 256 outputs, 64-deep steps
+using SplitTile128 = Tile<2, 2, 2, 4, 2>;   // same for r <= 128: 64 x 128 outputs
 constexpr int kSplitDepth = 3;
 using DmaTile = Tile<4, 1, 2, 16, 1>;    // fast path: 128 x 256 outputs, 32-deep steps, each
                                          // wave owns 32 rows (A read once per workgroup)
+using DmaTile128 = Tile<4, 1, 2, 8, 1>;  // fast path for r <= 128: 128 x 128 outputs
 constexpr int kDmaDepth = 6;             // pipeline stages (A registers, Omega LDS stages)
 constexpr bool kDmaTwoAcc = false;       // one accumulator (hi against 2^11 Omega); two spill at BM = 128
 using F32Tile = Tile<2, 2, 4, 4, 1>;     // 128 x 128 outputs, 32-deep steps
@@ -323,8 +325,11 @@ __device__ __forceinline__ void wait_vm_barrier() {
 // scheduling-group masks of __builtin_amdgcn_sched_group_barrier
 constexpr int kSchedValu = 0x002, kSchedMfma = 0x008, kSchedVmemRead = 0x020, kSchedDsRead = 0x100;
 
+// The body of the split-FP16 projection for output tile (bm, bn) and
+// contraction share kz of problem p; tiles_n = number of column tiles of p.
 template <class T, int D, bool TWO_ACC>
-__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(ProjArgs p) {
+__device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t bm, const int64_t bn,
+                                               const int kz, const int64_t tiles_n) {
     constexpr int STAGE = T::KS * T::NTB * 64;                 // 16-byte chunks per Omega stage
     constexpr int CH = STAGE / T::THREADS;                     // chunks per thread per stage
     constexpr int A_OPS = T::TM * T::KS * 2;                   // 16-byte A loads per step
@@ -354,8 +359,6 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int wm = wave % T::WM, wn = wave / T::WM;
-    const int64_t bm = blockIdx.x, bn = blockIdx.y;
-    const int kz = blockIdx.z;
 
     // this workgroup's share of the full contraction steps: [js, je)
     const int64_t nfull = p.n / T::BK;
@@ -546,7 +549,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
     if (p.ksplit > 1) {
         // partial sums in lane order (16 bytes per lane per fragment), then the
         // last workgroup of the tile adds all ksplit partials in order z = 0, 1, ...
-        const int64_t tile = bm * gridDim.y + bn;
+        const int64_t tile = bm * tiles_n + bn;
         constexpr int TILE_F4 = T::TM * T::TN * T::THREADS;      // float4s per partial tile
         floatx4* mine = reinterpret_cast<floatx4*>(p.partial) + (tile * p.ksplit + kz) * TILE_F4;
 #pragma unroll
@@ -585,6 +588,29 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(Pr
                     p.Y[row * p.ldy + col] = acc[tm][j][e] * 0x1p-11f;
             }
         }
+}
+
+template <class T, int D, bool TWO_ACC>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_dma_kernel(ProjArgs p) {
+    split_dma_body<T, D, TWO_ACC>(p, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
+}
+
+// Several independent projections in one launch: block b belongs to the
+// problem g with start[g] <= b < start[g+1]; inside it, blocks enumerate
+// (kz, bm, bn) with bn fastest.
+template <class T, int D, bool TWO_ACC>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kernel(GroupArgs ga) {
+    const int64_t b = blockIdx.x;
+    int g = 0;
+#pragma unroll 1
+    while (g + 1 < ga.count && b >= ga.start[g + 1]) ++g;
+    const ProjArgs& p = ga.prob[g];
+    const int64_t local = b - ga.start[g];
+    const int64_t tn = ga.tiles_n[g], tm = ga.tiles_m[g];
+    const int64_t per_k = tm * tn;
+    const int kz = (int)(local / per_k);
+    const int64_t rest = local - kz * per_k;
+    split_dma_body<T, D, TWO_ACC>(p, rest / tn, rest % tn, kz, tn);
 }
 
 // ------------------------------------------------------------------ FP32 kernel
@@ -713,6 +739,12 @@ bool vector_ok(const ProjArgs& a) {
            (a.s_k_outer & 3) == 0 && (a.k_inner & 3) == 0;
 }
 
+}  // namespace
+
+bool split_vector_ok(const ProjArgs& a) { return vector_ok(a); }
+
+namespace {
+
 int small_grid(int64_t total) {
     int64_t g = (total + 255) / 256;
     return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
@@ -720,20 +752,21 @@ int small_grid(int64_t total) {
 
 }  // namespace
 
-int64_t split_f16_col_block() { return SplitTile::BN; }
+int64_t split_f16_col_block(int64_t r) { return r <= 128 ? 128 : 256; }
 int64_t f32_col_block() { return F32Tile::BN; }
 int64_t proj_k_block() { return 64; }   // multiple of every tile's step (SplitTile 64, DmaTile 32, F32Tile 32)
 static_assert(64 % SplitTile::BK == 0 && 64 % DmaTile::BK == 0 && 64 % F32Tile::BK == 0, "k block");
-static_assert(SplitTile::BN == DmaTile::BN, "both split paths read the same packed Omega");
+static_assert(SplitTile::BN == DmaTile::BN && SplitTile128::BN == DmaTile128::BN && DmaTile128::BN == 128 &&
+              DmaTile::BN == 256, "both split paths read the same packed Omega");
 
-SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
-    using T = DmaTile;
+template <class T>
+SplitPlan plan_for(int64_t m, int64_t n, int64_t r, int num_cus) {
     SplitPlan plan{1, 0, 0};
     const int64_t tiles = ((m + T::BM - 1) / T::BM) * ((r + T::BN - 1) / T::BN);
     const int64_t nfull = n / T::BK;
     if (tiles <= 0 || nfull <= 0) return plan;
     int64_t k = num_cus / tiles;                 // fill the chip with tiles x k workgroups
-    k = k > 16 ? 16 : k;
+    k = k > 32 ? 32 : k;
     k = k > nfull / (2 * kDmaDepth) ? nfull / (2 * kDmaDepth) : k;   // keep shares >= 2 groups
     if (k < 2) return plan;
     plan.ksplit = (int)k;
@@ -742,18 +775,41 @@ SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
     return plan;
 }
 
-hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
+SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
+    return r <= 128 ? plan_for<DmaTile128>(m, n, r, num_cus) : plan_for<DmaTile>(m, n, r, num_cus);
+}
+
+int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
+int64_t split_group_tile_n(int64_t r) { return r <= 128 ? DmaTile128::BN : DmaTile::BN; }
+
+hipError_t launch_project_split_f16_grouped(const GroupArgs& ga, bool narrow, hipStream_t s) {
+    const int64_t blocks = ga.start[ga.count];
+    if (blocks <= 0) return hipSuccess;
+    if (narrow)
+        hipLaunchKernelGGL((project_split_f16_grouped_kernel<DmaTile128, kDmaDepth, kDmaTwoAcc>),
+                           dim3((unsigned)blocks), dim3(DmaTile128::THREADS), 0, s, ga);
+    else
+        hipLaunchKernelGGL((project_split_f16_grouped_kernel<DmaTile, kDmaDepth, kDmaTwoAcc>),
+                           dim3((unsigned)blocks), dim3(DmaTile::THREADS), 0, s, ga);
+    return hipGetLastError();
+}
+
+template <class TD, class TS>
+hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
     if (vector_ok(a)) {
-        using T = DmaTile;
-        dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN),
+        dim3 grid((unsigned)((a.m + TD::BM - 1) / TD::BM), (unsigned)((a.r + TD::BN - 1) / TD::BN),
                   (unsigned)(a.ksplit > 1 ? a.ksplit : 1));
-        hipLaunchKernelGGL((project_split_f16_dma_kernel<T, kDmaDepth, kDmaTwoAcc>), grid, dim3(T::THREADS), 0, s, a);
+        hipLaunchKernelGGL((project_split_f16_dma_kernel<TD, kDmaDepth, kDmaTwoAcc>), grid, dim3(TD::THREADS), 0,
+                           s, a);
     } else {
-        using T = SplitTile;
-        dim3 grid((unsigned)((a.m + T::BM - 1) / T::BM), (unsigned)((a.r + T::BN - 1) / T::BN));
-        hipLaunchKernelGGL((project_split_f16_kernel<T, kSplitDepth, false>), grid, dim3(T::THREADS), 0, s, a);
+        dim3 grid((unsigned)((a.m + TS::BM - 1) / TS::BM), (unsigned)((a.r + TS::BN - 1) / TS::BN));
+        hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, false>), grid, dim3(TS::THREADS), 0, s, a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
+    return a.r <= 128 ? launch_split_with<DmaTile128, SplitTile128>(a, s) : launch_split_with<DmaTile, SplitTile>(a, s);
 }
 
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {

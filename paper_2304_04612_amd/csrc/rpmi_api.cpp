@@ -218,7 +218,7 @@ bool proj_layout_ok(rp_ctx ctx, const rp_desc* A, rp_status* st) {
 
 rpmi::PackedOmega packed_geometry(int64_t n, int64_t r, rp_algo_t algo, void* data) {
     rpmi::PackedOmega pk;
-    const int64_t col_block = algo == RP_ALGO_SPLIT_F16 ? rpmi::split_f16_col_block() : rpmi::f32_col_block();
+    const int64_t col_block = algo == RP_ALGO_SPLIT_F16 ? rpmi::split_f16_col_block(r) : rpmi::f32_col_block();
     pk.kb_count = round_up(n, rpmi::proj_k_block()) / rpmi::kKBlock;
     pk.nt_count = round_up(r, col_block) / rpmi::kNTile;
     pk.data = data;
@@ -398,6 +398,139 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
     if ((st = fill_packed(ctx, seed, stream_id, omega, ldo, omega_type, n, r, algo, pk, raw, s)) != RP_OK)
         return st;
     return launch_projection(ctx, A, r, pk, algo, Y, ldy, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Bump allocator over the context workspace (256-byte aligned pieces).
+struct Arena {
+    size_t used = 0;
+    size_t take(size_t bytes) {
+        const size_t off = used;
+        used += (bytes + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+// CholeskyQR2 of the m x p matrix Y (FP32, leading dimension ldy):
+// Q (FP32, ldq) with orthonormal columns spanning Y, and, if M != NULL, the
+// p x p lower-triangular product L1 L2 of the two Cholesky factors
+// (= R^T for R = R2 R1, Y = Q R).  Scratch: Qd (m x p FP64), G, X (p x p FP64
+// each) and L1 (p x p FP64, kept only when M is requested).
+rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy, float* Q, int64_t ldq,
+                  double* M, double* Qd, double* G, double* X, double* L1, hipStream_t s) {
+    unsigned int* st = ctx->d_status;
+    // pass 1: G = Y^T Y, G = L L^T, X = L^-1, Qd = Y X^T  (= Y R^-1)
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, double>(p, p, m, 1.0, Y, 1, ldy, Y, ldy, 1, 0.0, G, p, 1, s)));
+    RP_HIP(ctx, rpmi::potrf_lower(G, p, p, st, s));
+    RP_HIP(ctx, rpmi::trtri_lower(G, p, X, p, p, s));
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, double>(m, p, p, 1.0, Y, ldy, 1, X, 1, p, 0.0, Qd, p, 1, s)));
+    if (M) RP_HIP(ctx, hipMemcpyAsync(L1, G, (size_t)p * p * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // pass 2 on Qd
+    RP_HIP(ctx, (rpmi::gemm_acc64<double, double, double>(p, p, m, 1.0, Qd, 1, p, Qd, p, 1, 0.0, G, p, 1, s)));
+    RP_HIP(ctx, rpmi::potrf_lower(G, p, p, st, s));
+    RP_HIP(ctx, rpmi::trtri_lower(G, p, X, p, p, s));
+    RP_HIP(ctx, (rpmi::gemm_acc64<double, double, float>(m, p, p, 1.0, Qd, p, 1, X, 1, p, 0.0, Q, ldq, 1, s)));
+    if (M) RP_HIP(ctx, (rpmi::gemm_acc64<double, double, double>(p, p, p, 1.0, L1, p, 1, G, p, 1, 0.0, M, p, 1, s)));
+    return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, int64_t k, int64_t oversample,
+               int32_t power_iters, uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* U, int64_t ldu,
+               double* S, float* VT, int64_t ldvt, void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    rp_status st;
+    if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    const int64_t p = k + oversample;
+    if (m <= 0 || n <= 0 || k <= 0 || oversample < 0 || power_iters < 0)
+        return fail(ctx, RP_ERR_INVALID_ARG, "invalid sizes (m %lld, n %lld, k %lld, s %lld, q %d)", (long long)m,
+                    (long long)n, (long long)k, (long long)oversample, (int)power_iters);
+    if (p > m || p > n || p > 1024)
+        return fail(ctx, RP_ERR_INVALID_ARG, "k + oversample = %lld must be <= min(m, n) and <= 1024", (long long)p);
+    if (!A || !U || !S || !VT) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    if (lda < n || ldu < k || ldvt < n) return fail(ctx, RP_ERR_INVALID_ARG, "leading dimension too small");
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+
+    rp_desc dA{A, m, n, lda, n, 1, 0};
+    if (!proj_layout_ok(ctx, &dA, &st)) return st;
+
+    // workspace layout
+    Arena ar;
+    rpmi::PackedOmega pk = packed_geometry(n, p, algo, nullptr);
+    const size_t o_pk = ar.take(packed_bytes(pk, algo));
+    const rpmi::PackedOmega pkw_geom = packed_geometry(n, p, RP_ALGO_F32, nullptr);   // W for Y = A W
+    const size_t o_pkw = ar.take(packed_bytes(pkw_geom, RP_ALGO_F32));
+    const size_t o_raw = ar.take(algo == RP_ALGO_F32 ? (size_t)n * p * 4 : 0);       // raw Omega (FP32 path)
+    const int64_t mx = m > n ? m : n;
+    const size_t o_y = ar.take((size_t)m * p * 4);        // Y (m x p)
+    const size_t o_q = ar.take((size_t)m * p * 4);        // Q (m x p)
+    const size_t o_z = ar.take((size_t)n * p * 4);        // Z / B^T (n x p)
+    const size_t o_w = ar.take((size_t)n * p * 4);        // W / Q_B (n x p)
+    const size_t o_qd = ar.take((size_t)mx * p * 8);      // FP64 Q of the first CholeskyQR pass
+    const size_t o_g = ar.take((size_t)p * p * 8);
+    const size_t o_x = ar.take((size_t)p * p * 8);
+    const size_t o_l1 = ar.take((size_t)p * p * 8);
+    const size_t o_mw = ar.take((size_t)p * p * 8);       // R_B^T -> Jacobi W
+    const size_t o_mv = ar.take((size_t)p * p * 8);       // Jacobi V
+    const size_t o_sig = ar.take((size_t)p * 8);
+    const size_t o_ord = ar.take((size_t)p * 4);
+    const size_t o_ur = ar.take((size_t)p * k * 8);
+    const size_t o_vr = ar.take((size_t)p * k * 8);
+    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
+    char* base = static_cast<char*>(ctx->ws);
+    pk.data = base + o_pk;
+    rpmi::PackedOmega pkw = pkw_geom;
+    pkw.data = base + o_pkw;
+    float* Y = reinterpret_cast<float*>(base + o_y);
+    float* Q = reinterpret_cast<float*>(base + o_q);
+    float* Z = reinterpret_cast<float*>(base + o_z);
+    float* W = reinterpret_cast<float*>(base + o_w);
+    double* Qd = reinterpret_cast<double*>(base + o_qd);
+    double* G = reinterpret_cast<double*>(base + o_g);
+    double* X = reinterpret_cast<double*>(base + o_x);
+    double* L1 = reinterpret_cast<double*>(base + o_l1);
+    double* MW = reinterpret_cast<double*>(base + o_mw);
+    double* MV = reinterpret_cast<double*>(base + o_mv);
+    double* sig = reinterpret_cast<double*>(base + o_sig);
+    int* ord = reinterpret_cast<int*>(base + o_ord);
+    double* Ur = reinterpret_cast<double*>(base + o_ur);
+    double* Vr = reinterpret_cast<double*>(base + o_vr);
+
+    // Algorithm 1 line 1: Y = A Omega
+    if ((st = fill_packed(ctx, seed, 0, nullptr, 0, omega_type, n, p, algo, pk, base + o_raw, s)) != RP_OK) return st;
+    if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s)) != RP_OK) return st;
+    // power scheme, re-orthonormalised
+    for (int32_t t = 0; t < power_iters; ++t) {
+        if ((st = cholqr2(ctx, m, p, Y, p, Q, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
+        // Z = A^T Q (n x p)
+        RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
+        if ((st = cholqr2(ctx, n, p, Z, p, W, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
+        // Y = A W (FP32 x FP32): the FP32 projection kernel with W (n x p) in
+        // fragment order
+        RP_HIP(ctx, rpmi::launch_pack_omega(W, true, n, p, p, pkw, true, s));
+        if ((st = launch_projection(ctx, &dA, p, pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
+    }
+    // Algorithm 1 line 2: Q = QR(Y)
+    if ((st = cholqr2(ctx, m, p, Y, p, Q, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
+    // line 3: B^T = A^T Q (n x p)
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
+    // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
+    if ((st = cholqr2(ctx, n, p, Z, p, W, p, MW, Qd, G, X, L1, s)) != RP_OK) return st;
+    // SVD of R_B^T = U_r S V_r^T: then B = U_r S (Q_B V_r)^T
+    RP_HIP(ctx, rpmi::jacobi_svd(MW, MV, (int)p, 40, 1e-14, ctx->d_status, s));
+    RP_HIP(ctx, rpmi::svd_finish(MW, MV, (int)p, (int)k, sig, ord, Ur, Vr, s));
+    RP_HIP(ctx, hipMemcpyAsync(S, sig, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // line 5: U = Q U_r[:, :k] (m x k); V^T = (Q_B V_r[:, :k])^T (k x n)
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, Q, p, 1, Ur, k, 1, 0.0, U, ldu, 1, s)));
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, W, p, 1, Vr, k, 1, 0.0, VT, 1, ldvt, s)));
+    return RP_OK;
 }
 
 rp_status rp_split_f16(rp_ctx ctx, const float* x, int64_t count, uint16_t* hi, uint16_t* lo,

@@ -54,6 +54,22 @@ struct ProjArgs {
     unsigned int* counters;           // one per output tile, zero between launches
 };
 
+// Several split-FP16 projections in one launch (all on the 16-byte aligned
+// path).  Problem g owns blocks [start[g], start[g+1]): tiles_m x tiles_n
+// output tiles times its contraction split prob[g].ksplit.
+constexpr int kMaxGroup = 8;
+struct GroupArgs {
+    int count;
+    ProjArgs prob[kMaxGroup];
+    int64_t tiles_m[kMaxGroup], tiles_n[kMaxGroup];
+    int64_t start[kMaxGroup + 1];
+};
+int64_t split_group_tile_m(int64_t r);
+int64_t split_group_tile_n(int64_t r);
+// all problems of one grouped launch use the same tile: narrow (r <= 128) or not
+hipError_t launch_project_split_f16_grouped(const GroupArgs& ga, bool narrow, hipStream_t s);
+bool split_vector_ok(const ProjArgs& a);
+
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
 // contraction split it will use; the counters must be zero initially.
 struct SplitPlan {
@@ -69,7 +85,7 @@ constexpr unsigned int kStatusNotConverged = 4u;
 
 // Column padding the packed Omega must provide for each algorithm: the
 // kernels read whole column blocks.
-int64_t split_f16_col_block();
+int64_t split_f16_col_block(int64_t r);   // 128 for r <= 128, else 256
 int64_t f32_col_block();
 int64_t proj_k_block();               // contraction rows per main-loop step
 
@@ -86,6 +102,21 @@ hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16
                              hipStream_t s);
 hipError_t launch_fill_f32(float* y, int64_t rows, int64_t cols, int64_t ld, float v,
                            hipStream_t s);
+
+// ---------------------------------------------------------------- linalg.hip
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                      const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
+                      hipStream_t s);
+hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, hipStream_t s);
+hipError_t launch_zero_upper(double* A, int64_t lda, int64_t p, hipStream_t s);
+hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t p, hipStream_t s);
+hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s);
+hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, unsigned int* status,
+                      hipStream_t s);
+hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
+                      double* Vr, hipStream_t s);
+hipError_t convert_f64_f32(const double* x, float* y, int64_t count, hipStream_t s);
 
 }  // namespace rpmi
 

@@ -1,0 +1,83 @@
+"""Randomized SVD (Algorithm 1 with the power scheme) on the GPU against the
+FP64 oracle on the same inputs and the same Omega.
+
+Singular values are unique, so they are compared directly; singular vectors
+only up to sign (and rotation inside clusters), so U and V are compared as
+projectors onto their span and through the reconstruction U S V^T."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, dev, host, rp
+from oracle import omega, rsvd as orsvd
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(a, k, s, q, seed, omega_type, algo):
+    u, sv, vt = rp().rsvd(dev(a), k, s, q, seed, omega_type, algo)
+    st = rp().rp_get_device_status(clear=True)
+    return host(u).astype(np.float64), host(sv), host(vt).astype(np.float64), st
+
+
+def _oracle(a, k, s, q, seed, omega_type):
+    n = a.shape[1]
+    om = omega.omega_f32(seed, 0, n, k + s) if omega_type == "f32" else omega.omega_f16(seed, 0, n, k + s)
+    return orsvd.rsvd(a.astype(np.float64), om, k, q)
+
+
+def _check(a, k, s, q, seed, omega_type, algo, sv_rtol, proj_tol):
+    u, sv, vt, st = _run(a, k, s, q, seed, omega_type, algo)
+    assert st == rp().RP_OK
+    uo, so, vto = _oracle(a, k, s, q, seed, omega_type)
+    assert np.all(np.diff(sv) <= 0)
+    np.testing.assert_allclose(sv, so, rtol=sv_rtol, atol=sv_rtol * so[0])
+    # orthonormal columns
+    assert np.abs(u.T @ u - np.eye(k)).max() < 1e-4
+    assert np.abs(vt @ vt.T - np.eye(k)).max() < 1e-4
+    # same subspaces (projectors), same reconstruction error
+    assert np.linalg.norm(u @ u.T - uo @ uo.T) < proj_tol
+    rec = np.linalg.norm(a - (u * sv) @ vt)
+    rec_o = np.linalg.norm(a - (uo * so) @ vto)
+    assert rec <= rec_o * (1 + 1e-3) + 1e-5 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("omega_type,algo", [("f32", "f32"), ("f16", "split_f16"), ("f16", "f32")])
+def test_rsvd_c1_shape(omega_type, algo):
+    """1024 x 1024, sigma_i = 0.9^i, k = 32, s = 32, q = 0 (the all-FP32 RSVD
+    workload, plus the FP16-Omega variants)."""
+    announce(f"rsvd 1024 {omega_type} {algo}")
+    a = synth.np_planted(1024, 1024, synth.sigma_geometric(1024, 0.9), np.random.default_rng(101))
+    _check(a, 32, 32, 0, 201, omega_type, algo, 2e-5, 1e-3)
+
+
+def test_rsvd_power_iteration_ragged():
+    announce("rsvd power iteration 700 x 530")
+    rng = np.random.default_rng(5)
+    sig = 1.0 / np.arange(1, 501) ** 0.7
+    a = synth.np_planted(700, 530, sig, rng)
+    _check(a, 37, 13, 1, 9, "f16", "split_f16", 5e-5, 5e-3)
+
+
+def test_rsvd_planted_rank_recovered():
+    announce("rsvd planted rank 20")
+    rng = np.random.default_rng(6)
+    sig = np.linspace(10.0, 1.0, 20)
+    a = synth.np_planted(900, 800, sig, rng)
+    u, sv, vt, st = _run(a, 20, 12, 0, 3, "f16", "split_f16")
+    assert st == rp().RP_OK
+    np.testing.assert_allclose(sv, sig, rtol=1e-5)
+    assert np.linalg.norm(a - (u * sv) @ vt) <= 2e-6 * np.linalg.norm(a)
+
+
+def test_rsvd_zero_matrix_reports_breakdown():
+    a = np.zeros((200, 150), np.float32)
+    u, sv, vt, st = _run(a, 5, 5, 0, 1, "f16", "split_f16")
+    assert st == rp().RP_ERR_NOT_SPD
+
+
+def test_rsvd_invalid_arguments():
+    import torch
+    a = torch.ones((50, 40), device="cuda")
+    with pytest.raises(rp().RpError):
+        rp().rsvd(a, 30, 20)          # k + s > min(m, n)
