@@ -201,6 +201,34 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
                float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* stream);
 
 /*
+ * Random-projection HOSVD (Algorithm 2, Sec. 2.3) of the ndim-way FP32 tensor
+ * X (C order, dims[0] x ... x dims[ndim-1], 2 <= ndim <= 8), with target
+ * ranks J_i = ranks[i] (oversampling included; 1 <= J_i <= dims[i],
+ * J_i <= prod_{l != i} dims[l], J_i <= 1024):
+ *     for each mode i:  W_i = X_(i) Omega_i;  Q_i = QR(W_i)
+ *     core = X x_1 Q_1^T x_2 Q_2^T ... x_N Q_N^T
+ * X_(i) is the mode-i unfolding: row index i_i, column index the C-order
+ * linear index of the remaining modes.  Omega_i (prod_{l != i} dims[l] x J_i)
+ * is generated from (seed, stream_id = i) in omega_type; the projections run
+ * with `algo` (RP_ALGO_SPLIT_F16: all modes whose unfolding can be streamed in
+ * place go out in one grouped launch; a mode whose columns are not contiguous
+ * in runs of a multiple of 64 elements, the last mode among them, is first
+ * copied mode-first into workspace).  Each QR is CholeskyQR2 (FP64 Gram,
+ * Cholesky and triangular inverse), so Q_i is the orthonormal factor with a
+ * positive-diagonal R.  The core contractions are FP32 products with FP64
+ * accumulation, one mode at a time.
+ * Outputs (device): core, C order J_0 x ... x J_{ndim-1} FP32; factors is a
+ * host array of ndim device pointers, factors[i] dims[i] x J_i row-major FP32.
+ * dims, ranks, factors: host arrays owned by the caller, read during the call.
+ * Device conditions: RP_ERR_NOT_SPD (a W_i numerically rank-deficient),
+ * RP_ERR_RANGE (split path, X outside the FP16 range).  Grows the context
+ * workspace as needed (synchronising the device then).
+ */
+rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X,
+                   const int64_t* ranks, uint64_t seed, rp_omega_t omega_type,
+                   rp_algo_t algo, float* core, float* const* factors, void* stream);
+
+/*
  * Split of an FP32 array into FP16 hi and lo (Sec. 4.1, eq:shgemm-1/2), as the
  * projection performs it in registers: hi = RN16(a), lo = RN16((a - hi) 2^11).
  * Exposed so that the split can be checked bit for bit.  x: count floats;

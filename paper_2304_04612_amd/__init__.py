@@ -67,6 +67,7 @@ def lib():
         "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, vp, i64, vp],
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
         "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, vp, i64, vp, vp, i64, vp],
+        "rp_hosvd": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -234,6 +235,29 @@ def rsvd(a, k, oversample=10, power_iters=0, seed=0, omega_type="f16", algo="spl
                                   OMEGA_TYPES[omega_type], ALGOS[algo], _ptr(u), u.stride(0), _ptr(sv),
                                   _ptr(vt), vt.stride(0), _stream()))
     return u, sv, vt
+
+
+def rp_hosvd(x, ranks, seed=0, omega_type="f16", algo="split_f16", ctx=None):
+    """Random-projection HOSVD (Algorithm 2) of the C-contiguous float32 CUDA
+    tensor ``x`` with per-mode ranks; Omega_i from stream i.  Returns
+    (core float32 of shape ranks, [factor_i float32 dims[i] x ranks[i]])."""
+    import torch
+    ctx = ctx or default_context()
+    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a C-contiguous float32 CUDA tensor")
+    nd = x.dim()
+    ranks = [int(r) for r in ranks]
+    if len(ranks) != nd:
+        raise ValueError("one rank per mode")
+    dev = f"cuda:{ctx.device}"
+    core = torch.empty(ranks, dtype=torch.float32, device=dev)
+    factors = [torch.empty((x.shape[i], ranks[i]), dtype=torch.float32, device=dev) for i in range(nd)]
+    dims_c = (ctypes.c_int64 * nd)(*x.shape)
+    ranks_c = (ctypes.c_int64 * nd)(*ranks)
+    fac_c = (ctypes.c_void_p * nd)(*[_ptr(f) for f in factors])
+    _check(ctx.handle, lib().rp_hosvd(ctx.handle, nd, dims_c, _ptr(x), ranks_c, seed, OMEGA_TYPES[omega_type],
+                                      ALGOS[algo], _ptr(core), fac_c, _stream()))
+    return core, factors
 
 
 def rp_get_device_status(clear=True, ctx=None):

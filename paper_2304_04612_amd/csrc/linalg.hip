@@ -34,11 +34,15 @@ __device__ __forceinline__ double ld(const T* p) { return (double)*p; }
 // B(k,j) = b[k*sbk + j*sbn], C[i][j] = c[i*scm + j*scn].  beta == 0 ignores C's
 // old contents (NaN included).  256 threads, each owning a 4x4 block of the
 // 64x64 tile.
+// Batched over blockIdx.z: problem z uses a + z*sab, b + z*sbb, c + z*scb.
 template <class TA, class TB, class TC>
 __global__ __launch_bounds__(256) void gemm_acc64_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ a, int64_t sam, int64_t sak,
     const TB* __restrict__ b, int64_t sbk, int64_t sbn, double beta, TC* __restrict__ c, int64_t scm,
-    int64_t scn) {
+    int64_t scn, int64_t sab, int64_t sbb, int64_t scb) {
+    a += blockIdx.z * sab;
+    b += blockIdx.z * sbb;
+    c += blockIdx.z * scb;
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
     const int tid = threadIdx.x;
@@ -324,11 +328,23 @@ template <class TA, class TB, class TC>
 hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
                       const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
                       hipStream_t s) {
-    if (M <= 0 || N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT));
-    hipLaunchKernelGGL((gemm_acc64_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M, N, K, alpha, a, sam, sak, b,
-                       sbk, sbn, beta, c, scm, scn);
-    return hipGetLastError();
+    return gemm_acc64_batched<TA, TB, TC>(M, N, K, alpha, a, sam, sak, 0, b, sbk, sbn, 0, beta, c, scm, scn, 0, 1, s);
+}
+
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                              int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
+                              int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    for (int64_t z0 = 0; z0 < batch; z0 += 65535) {
+        const int64_t nb = batch - z0 < 65535 ? batch - z0 : 65535;
+        dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)nb);
+        hipLaunchKernelGGL((gemm_acc64_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M, N, K, alpha, a + z0 * sab, sam,
+                           sak, b + z0 * sbb, sbk, sbn, beta, c + z0 * scb, scm, scn, sab, sbb, scb);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template hipError_t gemm_acc64<float, float, double>(int64_t, int64_t, int64_t, double, const float*, int64_t,
@@ -349,6 +365,61 @@ template hipError_t gemm_acc64<float, double, double>(int64_t, int64_t, int64_t,
 template hipError_t gemm_acc64<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
                                                     int64_t, const float*, int64_t, int64_t, double, float*,
                                                     int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64_batched<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                            int64_t, int64_t, const float*, int64_t, int64_t, int64_t,
+                                                            double, float*, int64_t, int64_t, int64_t, int64_t,
+                                                            hipStream_t);
+
+namespace {
+
+// dst[i][bb][aa] = src[bb][i][aa] for src of shape [B, I, P] (C order): the
+// mode-i unfolding of a C-order tensor made contiguous.  P == 1 is a plain
+// transpose, tiled through LDS so that reads and writes are both coalesced;
+// P > 1 copies runs of P contiguous elements.
+__global__ __launch_bounds__(256) void transpose_tile_kernel(const float* __restrict__ src, int64_t B, int64_t I,
+                                                             float* __restrict__ dst) {
+    __shared__ float t[32][33];
+    const int64_t b0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t bb = b0 + ty + 8 * q, ii = i0 + tx;
+        if (bb < B && ii < I) t[ty + 8 * q][tx] = src[bb * I + ii];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t ii = i0 + ty + 8 * q, bb = b0 + tx;
+        if (bb < B && ii < I) dst[ii * B + bb] = t[tx][ty + 8 * q];
+    }
+}
+
+__global__ __launch_bounds__(256) void swap01_kernel(const float* __restrict__ src, int64_t B, int64_t I, int64_t P,
+                                                     float* __restrict__ dst) {
+    const int64_t total = B * I * P;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t aa = e % P, rest = e / P;
+        const int64_t bb = rest % B, ii = rest / B;      // e indexes dst[ii][bb][aa]
+        dst[e] = src[(bb * I + ii) * P + aa];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_swap01(const float* src, int64_t B, int64_t I, int64_t P, float* dst, hipStream_t s) {
+    if (B <= 0 || I <= 0 || P <= 0) return hipSuccess;
+    if (P == 1) {
+        const int64_t gb = (B + 31) / 32, gi = (I + 31) / 32;
+        if (gi > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(transpose_tile_kernel, dim3((unsigned)gb, (unsigned)gi), dim3(256), 0, s, src, B, I, dst);
+    } else {
+        const int64_t total = B * I * P;
+        int64_t g = (total + 255) / 256;
+        g = g > 65536 ? 65536 : g;
+        hipLaunchKernelGGL(swap01_kernel, dim3((unsigned)g), dim3(256), 0, s, src, B, I, P, dst);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s) {
     hipLaunchKernelGGL(trtri_apply_diag_kernel, dim3((unsigned)((r0 + NB - 1) / NB)), dim3(256), 0, s, X, ldx, r0,

@@ -22,8 +22,10 @@ struct rp_ctx_s {
     size_t ws_bytes = 0;
     // contraction-split workspace of the split-FP16 projection: per-tile
     // counters (kept zero between launches) followed by partial sums
-    void* split_ws = nullptr;
+    void* split_ws = nullptr;            // split-K partial sums (scratch)
     size_t split_ws_bytes = 0;
+    unsigned int* split_counters = nullptr;   // per-tile arrival counters: zero
+    size_t split_counter_bytes = 0;           // between launches (reset by each tile's last workgroup)
     int num_cus = 0;
     std::string last_error;
 };
@@ -166,6 +168,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->d_status) (void)hipFree(ctx->d_status);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->split_ws) (void)hipFree(ctx->split_ws);
+    if (ctx->split_counters) (void)hipFree(ctx->split_counters);
     delete ctx;
     return RP_OK;
 }
@@ -267,21 +270,35 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
     return RP_OK;
 }
 
-// Grow the split workspace to hold `counters` zeroed counter bytes plus
-// `partials` bytes (synchronises the device when it grows).
+// Grow the split-K buffers: `counters` bytes of arrival counters in their own
+// allocation (zeroed when allocated; every launch leaves them zero) and
+// `partials` bytes of partial-sum scratch.  Synchronises the device when
+// either grows.
 rp_status ensure_split_workspace(rp_ctx ctx, size_t counters, size_t partials) {
-    const size_t need = ((counters + 255) & ~size_t(255)) + partials;
-    if (need <= ctx->split_ws_bytes) return RP_OK;
-    RP_HIP(ctx, hipDeviceSynchronize());
-    if (ctx->split_ws) {
-        RP_HIP(ctx, hipFree(ctx->split_ws));
-        ctx->split_ws = nullptr;
-        ctx->split_ws_bytes = 0;
+    if (counters > ctx->split_counter_bytes) {
+        RP_HIP(ctx, hipDeviceSynchronize());
+        if (ctx->split_counters) {
+            RP_HIP(ctx, hipFree(ctx->split_counters));
+            ctx->split_counters = nullptr;
+            ctx->split_counter_bytes = 0;
+        }
+        const size_t bytes = (counters + 0xFFFF) & ~size_t(0xFFFF);
+        RP_HIP(ctx, hipMalloc(&ctx->split_counters, bytes));
+        RP_HIP(ctx, hipMemset(ctx->split_counters, 0, bytes));
+        RP_HIP(ctx, hipDeviceSynchronize());
+        ctx->split_counter_bytes = bytes;
     }
-    const size_t bytes = (need + 0xFFFFF) & ~size_t(0xFFFFF);
-    RP_HIP(ctx, hipMalloc(&ctx->split_ws, bytes));
-    RP_HIP(ctx, hipMemset(ctx->split_ws, 0, bytes));
-    ctx->split_ws_bytes = bytes;
+    if (partials > ctx->split_ws_bytes) {
+        RP_HIP(ctx, hipDeviceSynchronize());
+        if (ctx->split_ws) {
+            RP_HIP(ctx, hipFree(ctx->split_ws));
+            ctx->split_ws = nullptr;
+            ctx->split_ws_bytes = 0;
+        }
+        const size_t bytes = (partials + 0xFFFFF) & ~size_t(0xFFFFF);
+        RP_HIP(ctx, hipMalloc(&ctx->split_ws, bytes));
+        ctx->split_ws_bytes = bytes;
+    }
     return RP_OK;
 }
 
@@ -302,14 +319,64 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
             rp_status st = ensure_split_workspace(ctx, plan.counter_bytes, plan.partial_bytes);
             if (st != RP_OK) return st;
             a.ksplit = plan.ksplit;
-            a.counters = static_cast<unsigned int*>(ctx->split_ws);
-            a.partial = reinterpret_cast<float*>(static_cast<char*>(ctx->split_ws) +
-                                                 ((plan.counter_bytes + 255) & ~size_t(255)));
+            a.counters = ctx->split_counters;
+            a.partial = static_cast<float*>(ctx->split_ws);
         }
         RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
     } else {
         RP_HIP(ctx, rpmi::launch_project_f32(a, s));
     }
+    return RP_OK;
+}
+
+// Several split-FP16 projections in one grouped launch (every problem on the
+// 16-byte path, all with r <= 128 or all with r > 128); the contraction split
+// of each problem is planned for its share of the compute units, in
+// proportion to its A bytes.  Returns RP_ERR_UNSUPPORTED (nothing launched)
+// when the problems do not qualify; the caller then launches them one by one.
+rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const* A, const int64_t* r,
+                                    const rpmi::PackedOmega* pk, float* const* Y, const int64_t* ldy,
+                                    hipStream_t s) {
+    if (count <= 0 || count > rpmi::kMaxGroup) return RP_ERR_UNSUPPORTED;
+    const bool narrow = r[0] <= 128;
+    rpmi::GroupArgs ga;
+    ga.count = count;
+    double total = 0;
+    for (int g = 0; g < count; ++g) total += (double)A[g]->rows * A[g]->cols;
+    const int cus = ctx->num_cus > 0 ? ctx->num_cus : 256;
+    size_t counter_bytes = 0, partial_bytes = 0;
+    rpmi::SplitPlan plans[rpmi::kMaxGroup];
+    for (int g = 0; g < count; ++g) {
+        if ((r[g] <= 128) != narrow || A[g]->rows == 0 || A[g]->cols == 0 || r[g] == 0) return RP_ERR_UNSUPPORTED;
+        rpmi::ProjArgs& a = ga.prob[g];
+        a.A = A[g]->ptr; a.m = A[g]->rows; a.n = A[g]->cols;
+        a.s_row = A[g]->s_row; a.k_inner = A[g]->k_inner; a.s_k_outer = A[g]->s_k_outer;
+        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
+        a.Y = Y[g]; a.ldy = ldy[g]; a.r = r[g];
+        a.status = ctx->d_status;
+        if (!rpmi::split_vector_ok(a)) return RP_ERR_UNSUPPORTED;
+        int share = (int)(cus * ((double)a.m * a.n / total) + 0.5);
+        plans[g] = rpmi::plan_split_f16(a.m, a.n, a.r, share > 0 ? share : 1);
+        counter_bytes += (plans[g].counter_bytes + 255) & ~size_t(255);
+        partial_bytes += (plans[g].partial_bytes + 255) & ~size_t(255);
+    }
+    rp_status st = ensure_split_workspace(ctx, counter_bytes, partial_bytes);
+    if (st != RP_OK) return st;
+    char* cbase = reinterpret_cast<char*>(ctx->split_counters);
+    char* pbase = static_cast<char*>(ctx->split_ws);
+    ga.start[0] = 0;
+    for (int g = 0; g < count; ++g) {
+        rpmi::ProjArgs& a = ga.prob[g];
+        a.ksplit = plans[g].ksplit;
+        a.counters = a.ksplit > 1 ? reinterpret_cast<unsigned int*>(cbase) : nullptr;
+        a.partial = a.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
+        cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
+        pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
+        ga.tiles_m[g] = (a.m + rpmi::split_group_tile_m(a.r) - 1) / rpmi::split_group_tile_m(a.r);
+        ga.tiles_n[g] = (a.r + rpmi::split_group_tile_n(a.r) - 1) / rpmi::split_group_tile_n(a.r);
+        ga.start[g + 1] = ga.start[g] + ga.tiles_m[g] * ga.tiles_n[g] * a.ksplit;
+    }
+    RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ga, narrow, s));
     return RP_OK;
 }
 
@@ -530,6 +597,166 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     // line 5: U = Q U_r[:, :k] (m x k); V^T = (Q_B V_r[:, :k])^T (k x n)
     RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, Q, p, 1, Ur, k, 1, 0.0, U, ldu, 1, s)));
     RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, W, p, 1, Vr, k, 1, 0.0, VT, 1, ldvt, s)));
+    return RP_OK;
+}
+
+rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X, const int64_t* ranks,
+                   uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* core, float* const* factors,
+                   void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    rp_status st;
+    if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (ndim < 2 || ndim > rpmi::kMaxGroup)
+        return fail(ctx, RP_ERR_INVALID_ARG, "ndim %d outside [2, %d]", (int)ndim, rpmi::kMaxGroup);
+    if (!dims || !ranks || !X || !core || !factors) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    const int N = ndim;
+    int64_t total = 1;
+    for (int i = 0; i < N; ++i) {
+        if (dims[i] <= 0) return fail(ctx, RP_ERR_INVALID_ARG, "dims[%d] = %lld", i, (long long)dims[i]);
+        total *= dims[i];
+    }
+    for (int i = 0; i < N; ++i) {
+        const int64_t cols = total / dims[i];
+        if (ranks[i] <= 0 || ranks[i] > dims[i] || ranks[i] > cols || ranks[i] > 1024)
+            return fail(ctx, RP_ERR_INVALID_ARG, "ranks[%d] = %lld must be in [1, min(dims[%d], %lld, 1024)]", i,
+                        (long long)ranks[i], i, (long long)cols);
+        if (!factors[i]) return fail(ctx, RP_ERR_INVALID_ARG, "factors[%d] is NULL", i);
+    }
+    if (reinterpret_cast<uintptr_t>(X) & 3) return fail(ctx, RP_ERR_INVALID_ARG, "X is not 4-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+
+    // mode-i unfolding of the C-order tensor: rows i_i, columns the C-order
+    // index of the other modes = (leading index) * after + (trailing index);
+    // element offset = i_i * after + lead * (dims[i] * after) + trail
+    int64_t after[rpmi::kMaxGroup], before[rpmi::kMaxGroup];
+    for (int i = N - 1, a = 1; i >= 0; --i) { after[i] = a; a *= dims[i]; }
+    for (int i = 0; i < N; ++i) before[i] = total / (dims[i] * after[i]);
+    rp_desc desc[rpmi::kMaxGroup];
+    bool permuted[rpmi::kMaxGroup];
+    int64_t maxr = 0, maxd = 0, perm_elems = 0;
+    for (int i = 0; i < N; ++i) {
+        const int64_t cols = total / dims[i];
+        desc[i] = rp_desc{X, dims[i], cols, after[i], after[i] == 1 && before[i] > 1 ? 1 : after[i], 1,
+                          dims[i] * after[i]};
+        if (before[i] == 1) desc[i].k_inner = cols;             // mode 1: plain row-major
+        rp_status dummy;
+        permuted[i] = !(before[i] == 1 || (after[i] % rpmi::proj_k_block() == 0 && after[i] > 1));
+        if (!permuted[i] && !proj_layout_ok(ctx, &desc[i], &dummy)) permuted[i] = true;
+        if (permuted[i]) perm_elems = total;
+        maxr = ranks[i] > maxr ? ranks[i] : maxr;
+        maxd = dims[i] > maxd ? dims[i] : maxd;
+    }
+    // core intermediates: after contracting modes 0..i, shape [J_0..J_i, I_{i+1}..]
+    int64_t tmax = 0;
+    {
+        int64_t lead = 1;
+        for (int i = 0; i < N - 1; ++i) {
+            lead *= ranks[i];
+            const int64_t e = lead * after[i];
+            tmax = e > tmax ? e : tmax;
+        }
+    }
+    Arena ar;
+    size_t o_pk[rpmi::kMaxGroup], o_w[rpmi::kMaxGroup];
+    rpmi::PackedOmega pk[rpmi::kMaxGroup];
+    size_t raw_bytes = 0;
+    for (int i = 0; i < N; ++i) {
+        const int64_t cols = total / dims[i];
+        pk[i] = packed_geometry(cols, ranks[i], algo, nullptr);
+        o_pk[i] = ar.take(packed_bytes(pk[i], algo));
+        o_w[i] = ar.take((size_t)dims[i] * ranks[i] * 4);
+        if (algo == RP_ALGO_F32) {
+            const size_t rb = (size_t)cols * ranks[i] * (omega_type == RP_OMEGA_F32 ? 4 : 2);
+            raw_bytes = rb > raw_bytes ? rb : raw_bytes;
+        }
+    }
+    const size_t o_raw = ar.take(raw_bytes);
+    const size_t o_perm = ar.take((size_t)perm_elems * 4);
+    const size_t o_qd = ar.take((size_t)maxd * maxr * 8);
+    const size_t o_g = ar.take((size_t)maxr * maxr * 8);
+    const size_t o_x = ar.take((size_t)maxr * maxr * 8);
+    const size_t o_l1 = ar.take((size_t)maxr * maxr * 8);
+    const size_t o_t0 = ar.take((size_t)tmax * 4);
+    const size_t o_t1 = ar.take((size_t)tmax * 4);
+    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
+    char* base = static_cast<char*>(ctx->ws);
+    float* W[rpmi::kMaxGroup];
+    int64_t ldw[rpmi::kMaxGroup];
+    const rp_desc* dp[rpmi::kMaxGroup];
+    float* perm = reinterpret_cast<float*>(base + o_perm);
+
+    // Algorithm 2, first loop: W_i = X_(i) Omega_i, Omega_i from stream i.
+    // Modes whose unfolding the projection cannot stream in place are first
+    // copied mode-first into one scratch tensor (one mode at a time, so those
+    // projections run separately).
+    for (int i = 0; i < N; ++i) {
+        pk[i].data = base + o_pk[i];
+        W[i] = reinterpret_cast<float*>(base + o_w[i]);
+        ldw[i] = ranks[i];
+        dp[i] = &desc[i];
+        const int64_t cols = total / dims[i];
+        if ((st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, omega_type, cols, ranks[i], algo, pk[i],
+                              base + o_raw, s)) != RP_OK)
+            return st;
+    }
+    bool grouped_done = false;
+    if (algo == RP_ALGO_SPLIT_F16) {
+        const rp_desc* gA[rpmi::kMaxGroup];
+        int64_t gr[rpmi::kMaxGroup], gld[rpmi::kMaxGroup];
+        rpmi::PackedOmega gpk[rpmi::kMaxGroup];
+        float* gY[rpmi::kMaxGroup];
+        int cnt = 0;
+        for (int i = 0; i < N; ++i) {
+            if (permuted[i]) continue;
+            gA[cnt] = dp[i]; gr[cnt] = ranks[i]; gld[cnt] = ldw[i]; gpk[cnt] = pk[i]; gY[cnt] = W[i];
+            ++cnt;
+        }
+        bool same_width = true;
+        for (int g = 1; g < cnt; ++g) same_width = same_width && ((gr[g] <= 128) == (gr[0] <= 128));
+        if (cnt > 1 && same_width) {
+            st = launch_projection_grouped(ctx, cnt, gA, gr, gpk, gY, gld, s);
+            if (st == RP_OK) grouped_done = true;
+            else if (st != RP_ERR_UNSUPPORTED) return st;
+        }
+    }
+    for (int i = 0; i < N; ++i) {
+        if (permuted[i]) {
+            RP_HIP(ctx, rpmi::launch_swap01(X, before[i], dims[i], after[i], perm, s));
+            const int64_t cols = total / dims[i];
+            const rp_desc pd{perm, dims[i], cols, cols, cols, 1, 0};
+            if ((st = launch_projection(ctx, &pd, ranks[i], pk[i], algo, W[i], ldw[i], s)) != RP_OK) return st;
+        } else if (!grouped_done) {
+            if ((st = launch_projection(ctx, dp[i], ranks[i], pk[i], algo, W[i], ldw[i], s)) != RP_OK) return st;
+        }
+    }
+    // Q_i = QR(W_i) straight into the caller's factors
+    double* Qd = reinterpret_cast<double*>(base + o_qd);
+    double* G = reinterpret_cast<double*>(base + o_g);
+    double* Xs = reinterpret_cast<double*>(base + o_x);
+    double* L1 = reinterpret_cast<double*>(base + o_l1);
+    for (int i = 0; i < N; ++i)
+        if ((st = cholqr2(ctx, dims[i], ranks[i], W[i], ldw[i], factors[i], ranks[i], nullptr, Qd, G, Xs, L1, s)) !=
+            RP_OK)
+            return st;
+    // core g = X x_1 Q_1^T ... x_N Q_N^T, one mode at a time: T has shape
+    // [lead, I_i, after_i]; out[b][j][p] = sum_k Q_i[k][j] T[b][k][p]
+    const float* T = X;
+    float* bufs[2] = {reinterpret_cast<float*>(base + o_t0), reinterpret_cast<float*>(base + o_t1)};
+    int64_t lead = 1;
+    for (int i = 0; i < N; ++i) {
+        float* out = i == N - 1 ? core : bufs[i & 1];
+        const int64_t J = ranks[i], I = dims[i], P = after[i];
+        if (P == 1) {
+            RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(lead, J, I, 1.0, T, I, 1, factors[i], J, 1, 0.0, out, J,
+                                                                1, s)));
+        } else {
+            RP_HIP(ctx, (rpmi::gemm_acc64_batched<float, float, float>(J, P, I, 1.0, factors[i], 1, J, 0, T, P, 1,
+                                                                        I * P, 0.0, out, P, 1, J * P, lead, s)));
+        }
+        T = out;
+        lead *= J;
+    }
     return RP_OK;
 }
 

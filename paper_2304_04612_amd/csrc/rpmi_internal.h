@@ -68,6 +68,8 @@ int64_t split_group_tile_m(int64_t r);
 int64_t split_group_tile_n(int64_t r);
 // all problems of one grouped launch use the same tile: narrow (r <= 128) or not
 hipError_t launch_project_split_f16_grouped(const GroupArgs& ga, bool narrow, hipStream_t s);
+hipError_t launch_split_group_wide(const GroupArgs& ga, hipStream_t s);     // r > 128
+hipError_t launch_split_group_narrow(const GroupArgs& ga, hipStream_t s);   // r <= 128
 bool split_vector_ok(const ProjArgs& a);
 
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
@@ -108,6 +110,12 @@ template <class TA, class TB, class TC>
 hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
                       const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
                       hipStream_t s);
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                              int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
+                              int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s);
+// dst[i][b][p] = src[b][i][p], src of shape [B, I, P] in C order
+hipError_t launch_swap01(const float* src, int64_t B, int64_t I, int64_t P, float* dst, hipStream_t s);
 hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, hipStream_t s);
 hipError_t launch_zero_upper(double* A, int64_t lda, int64_t p, hipStream_t s);
 hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t p, hipStream_t s);

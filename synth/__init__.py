@@ -72,7 +72,7 @@ def np_tucker(dims, core_dims, rng, noise_std=0.0):
         x = np.moveaxis(np.tensordot(u, x, axes=([1], [mode])), 0, mode)
     if noise_std:
         x = x + noise_std * rng.standard_normal(dims)
-    return x.astype(np.float32)
+    return np.ascontiguousarray(x, dtype=np.float32)
 
 
 def batched_problem_list(count, seed, lo=512, hi=8192, kmin=16, kmax=128):
