@@ -201,6 +201,59 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
                float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* stream);
 
 /*
+ * One projection of a grouped call: Y = A Omega with Omega (A.cols x r, FP16)
+ * generated from (seed, stream_id).  A, Y: device, caller-owned.
+ */
+typedef struct {
+    rp_desc A;
+    int64_t r;
+    uint64_t seed;
+    uint32_t stream_id;
+    float* Y;
+    int64_t ldy;
+} rp_project_problem;
+
+/*
+ * Several split-FP16 projections (Sec. 4.1) of independent shapes: the
+ * problems whose A is on the 16-byte path go out in one grouped launch per
+ * column width (r <= 128, r > 128), each problem's contraction split planned
+ * for its share of the compute units; the others are launched one by one.
+ * omega_type must be RP_OMEGA_F16.  probs: host array of count problems,
+ * read during the call.  Same device conditions as rp_project.
+ */
+rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem* probs,
+                             rp_omega_t omega_type, void* stream);
+
+/* One randomized SVD of a batched call (arguments as in rsvd). */
+typedef struct {
+    int64_t m, n;
+    const float* A;
+    int64_t lda;
+    int64_t k, oversample;
+    float* U;
+    int64_t ldu;
+    double* S;
+    float* VT;
+    int64_t ldvt;
+} rp_rsvd_problem;
+
+/*
+ * Many randomized SVDs (Algorithm 1) of different shapes in one call:
+ * Omega_j from (seed, stream_id = j); RP_OMEGA_F16 takes the split-FP16
+ * projection, RP_OMEGA_F32 the FP32 one.  The projections of all problems go
+ * out in grouped launches whose contraction split is tuned once per
+ * problem-shape signature (the grouped projection is timed at a few
+ * compute-unit shares; the fastest is kept in the context).  The whole
+ * sequence (Omega generation, projections, every problem's CholeskyQR2,
+ * B, SVD and U, V^T stages) is captured in a HIP graph on a context stream
+ * and launched on `stream`; a later call with the same problems, buffers and
+ * options replays the graph, which reads A afresh.  The first call of a
+ * problem set synchronises the device.  Outputs per problem as in rsvd.
+ */
+rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, int32_t power_iters,
+                       uint64_t seed, rp_omega_t omega_type, void* stream);
+
+/*
  * Random-projection HOSVD (Algorithm 2, Sec. 2.3) of the ndim-way FP32 tensor
  * X (C order, dims[0] x ... x dims[ndim-1], 2 <= ndim <= 8), with target
  * ranks J_i = ranks[i] (oversampling included; 1 <= J_i <= dims[i],

@@ -42,6 +42,17 @@ class rp_desc(ctypes.Structure):
                 ("s_k_inner", ctypes.c_int64), ("s_k_outer", ctypes.c_int64)]
 
 
+class rp_project_problem(ctypes.Structure):
+    _fields_ = [("A", rp_desc), ("r", ctypes.c_int64), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64)]
+
+
+class rp_rsvd_problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("oversample", ctypes.c_int64), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("S", ctypes.c_void_p), ("VT", ctypes.c_void_p), ("ldvt", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -68,6 +79,8 @@ def lib():
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
         "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, vp, i64, vp, vp, i64, vp],
         "rp_hosvd": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
+        "rp_project_grouped": [vp, i32, vp, i32, vp],
+        "rsvd_batched": [vp, i32, vp, i32, u64, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -135,9 +148,12 @@ def desc_from_tensor(a, k_inner=None, s_k_outer=0, rows=None, cols=None, s_row=N
     if a.dtype != torch.float32 or not a.is_cuda:
         raise TypeError("A must be a float32 CUDA tensor")
     if rows is None:
-        if a.dim() != 2 or a.stride(1) != 1:
+        if a.dim() == 2 and a.numel() == 0:
+            rows, cols, s_row = a.shape[0], a.shape[1], max(a.shape[1], 1)
+        elif a.dim() != 2 or a.stride(1) != 1:
             raise ValueError("A must be 2-D with unit column stride (or give an explicit layout)")
-        rows, cols, s_row = a.shape[0], a.shape[1], a.stride(0)
+        else:
+            rows, cols, s_row = a.shape[0], a.shape[1], a.stride(0)
     k_inner = cols if k_inner is None else k_inner
     return rp_desc(a.data_ptr(), rows, cols, s_row, max(k_inner, 1), 1, s_k_outer)
 
@@ -258,6 +274,56 @@ def rp_hosvd(x, ranks, seed=0, omega_type="f16", algo="split_f16", ctx=None):
     _check(ctx.handle, lib().rp_hosvd(ctx.handle, nd, dims_c, _ptr(x), ranks_c, seed, OMEGA_TYPES[omega_type],
                                       ALGOS[algo], _ptr(core), fac_c, _stream()))
     return core, factors
+
+
+def rp_project_grouped(problems, omega_type="f16", ctx=None):
+    """Grouped split-FP16 projections.  ``problems``: list of (a, r, seed,
+    stream_id) with ``a`` a 2-D float32 CUDA tensor (unit column stride).
+    Returns the list of Y (float32, rows(a) x r)."""
+    import torch
+    ctx = ctx or default_context()
+    n = len(problems)
+    arr = (rp_project_problem * max(n, 1))()
+    ys = []
+    for i, (a, r, seed, sid) in enumerate(problems):
+        y = torch.empty((a.shape[0], r), dtype=torch.float32, device=f"cuda:{ctx.device}")
+        ys.append(y)
+        arr[i].A = desc_from_tensor(a)
+        arr[i].r, arr[i].seed, arr[i].stream_id = r, seed, sid
+        arr[i].Y, arr[i].ldy = _ptr(y), max(r, 1)
+    _check(ctx.handle, lib().rp_project_grouped(ctx.handle, n, arr, OMEGA_TYPES[omega_type], _stream()))
+    return ys
+
+
+def rsvd_batched(mats, ks, oversamples, power_iters=0, seed=0, omega_type="f16", outputs=None, ctx=None):
+    """Batched randomized SVD (Algorithm 1 per matrix; Omega_j from stream j).
+    ``mats``: list of 2-D float32 CUDA tensors.  ``outputs``: optional list of
+    (U, S, VT) to write into (a repeated call with the same tensors replays the
+    captured graph).  Returns the list of (U, S, VT)."""
+    import torch
+    ctx = ctx or default_context()
+    n = len(mats)
+    arr = (rp_rsvd_problem * max(n, 1))()
+    outs = []
+    dev = f"cuda:{ctx.device}"
+    for i, a in enumerate(mats):
+        if a.dtype != torch.float32 or not a.is_cuda or a.dim() != 2 or a.stride(1) != 1:
+            raise TypeError("matrices must be 2-D float32 CUDA tensors with unit column stride")
+        m, nn = a.shape
+        k = ks[i]
+        if outputs is not None:
+            u, sv, vt = outputs[i]
+        else:
+            u = torch.empty((m, k), dtype=torch.float32, device=dev)
+            sv = torch.empty((k,), dtype=torch.float64, device=dev)
+            vt = torch.empty((k, nn), dtype=torch.float32, device=dev)
+        outs.append((u, sv, vt))
+        arr[i].m, arr[i].n, arr[i].A, arr[i].lda = m, nn, _ptr(a), a.stride(0)
+        arr[i].k, arr[i].oversample = k, oversamples[i]
+        arr[i].U, arr[i].ldu, arr[i].S = _ptr(u), u.stride(0), _ptr(sv)
+        arr[i].VT, arr[i].ldvt = _ptr(vt), vt.stride(0)
+    _check(ctx.handle, lib().rsvd_batched(ctx.handle, n, arr, power_iters, seed, OMEGA_TYPES[omega_type], _stream()))
+    return outs
 
 
 def rp_get_device_status(clear=True, ctx=None):

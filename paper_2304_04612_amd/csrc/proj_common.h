@@ -507,17 +507,22 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
 }
 
 // Several independent projections in one launch: block b belongs to the
-// problem g with start[g] <= b < start[g+1]; inside it, blocks enumerate
-// (kz, bm, bn) with bn fastest.
+// problem g with table[g].start <= b < table[g + 1].start (binary search);
+// inside it, blocks enumerate (kz, bm, bn) with bn fastest.
 template <class T, int D, bool TWO_ACC>
-__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kernel(GroupArgs ga) {
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kernel(const GroupEntry* __restrict__ table,
+                                                                                 int count) {
     const int64_t b = blockIdx.x;
-    int g = 0;
+    int lo = 0, hi = count - 1;
 #pragma unroll 1
-    while (g + 1 < ga.count && b >= ga.start[g + 1]) ++g;
-    const ProjArgs& p = ga.prob[g];
-    const int64_t local = b - ga.start[g];
-    const int64_t tn = ga.tiles_n[g], tm = ga.tiles_m[g];
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ProjArgs p = table[lo].p;
+    const int64_t local = b - table[lo].start;
+    const int64_t tn = table[lo].tiles_n, tm = table[lo].tiles_m;
     const int64_t per_k = tm * tn;
     const int kz = (int)(local / per_k);
     const int64_t rest = local - kz * per_k;

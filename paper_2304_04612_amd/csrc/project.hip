@@ -297,31 +297,36 @@ SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
 int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
 int64_t split_group_tile_n(int64_t r) { return r <= 128 ? DmaTile128::BN : DmaTile::BN; }
 
-hipError_t launch_project_split_f16_grouped(const GroupArgs& ga, bool narrow, hipStream_t s) {
-    return narrow ? launch_split_group_narrow(ga, s) : launch_split_group_wide(ga, s);
+hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
+                                            hipStream_t s) {
+    return narrow ? launch_split_group_narrow(table, count, blocks, s) : launch_split_group_wide(table, count, blocks, s);
 }
 
+// The deep-pipeline kernel reads its problem from a device table; a single
+// projection passes a one-entry table through the launch's own argument
+// block (table_slot: device memory for one entry, owned by the caller).
 template <class C, class TS>
-hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
+hipError_t launch_split_with(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s) {
     using TD = typename C::Tile;
     if (vector_ok(a)) {
-        // a group of one: the deep-pipeline kernel exists only in grouped form
-        GroupArgs ga;
-        ga.count = 1;
-        ga.prob[0] = a;
-        ga.tiles_m[0] = (a.m + TD::BM - 1) / TD::BM;
-        ga.tiles_n[0] = (a.r + TD::BN - 1) / TD::BN;
-        ga.start[0] = 0;
-        ga.start[1] = ga.tiles_m[0] * ga.tiles_n[0] * (a.ksplit > 1 ? a.ksplit : 1);
-        return launch_project_split_f16_grouped(ga, TD::BN == 128, s);
+        GroupEntry e;
+        e.p = a;
+        e.tiles_m = (a.m + TD::BM - 1) / TD::BM;
+        e.tiles_n = (a.r + TD::BN - 1) / TD::BN;
+        e.start = 0;
+        const hipError_t err = hipMemcpyAsync(table_slot, &e, sizeof e, hipMemcpyHostToDevice, s);
+        if (err != hipSuccess) return err;
+        return launch_project_split_f16_grouped(table_slot, 1, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
+                                                TD::BN == 128, s);
     }
     dim3 grid((unsigned)((a.m + TS::BM - 1) / TS::BM), (unsigned)((a.r + TS::BN - 1) / TS::BN));
     hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, false>), grid, dim3(TS::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
-    return a.r <= 128 ? launch_split_with<NarrowCfg, SplitTile128>(a, s) : launch_split_with<WideCfg, SplitTile>(a, s);
+hipError_t launch_project_split_f16(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s) {
+    return a.r <= 128 ? launch_split_with<NarrowCfg, SplitTile128>(a, table_slot, s)
+                      : launch_split_with<WideCfg, SplitTile>(a, table_slot, s);
 }
 
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {

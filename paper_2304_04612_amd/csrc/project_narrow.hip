@@ -5,12 +5,11 @@
 
 namespace rpmi {
 
-hipError_t launch_split_group_narrow(const GroupArgs& ga, hipStream_t s) {
-    const int64_t blocks = ga.start[ga.count];
-    if (blocks <= 0) return hipSuccess;
+hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, hipStream_t s) {
+    if (blocks <= 0 || count <= 0) return hipSuccess;
     using T = NarrowCfg::Tile;
     hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, NarrowCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
-                       dim3(T::THREADS), 0, s, ga);
+                       dim3(T::THREADS), 0, s, table, count);
     return hipGetLastError();
 }
 

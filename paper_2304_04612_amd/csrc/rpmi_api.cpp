@@ -7,6 +7,7 @@
 
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rpmi.h"
@@ -24,10 +25,21 @@ struct rp_ctx_s {
     // counters (kept zero between launches) followed by partial sums
     void* split_ws = nullptr;            // split-K partial sums (scratch)
     size_t split_ws_bytes = 0;
+    rpmi::GroupEntry* table = nullptr;    // problem tables of grouped projections (device)
+    size_t table_entries = 0;
     unsigned int* split_counters = nullptr;   // per-tile arrival counters: zero
     size_t split_counter_bytes = 0;           // between launches (reset by each tile's last workgroup)
     int num_cus = 0;
     std::string last_error;
+    // batched RSVD: the captured graph of the last problem set (replayed while
+    // the set, its buffers and the context buffers are unchanged), its own
+    // device table of grouped projections, and the autotuner's choices
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    rpmi::GroupEntry* graph_table = nullptr;
+    size_t graph_table_entries = 0;
+    std::unordered_map<uint64_t, double> tuned_scale;
 };
 
 namespace {
@@ -155,6 +167,8 @@ rp_status rp_create(rp_ctx* out, int device) {
     if ((e = hipMemcpy(ctx->d_guide, guide.data(), guide.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(e, "hipMemcpy");
     if ((e = hipMemset(ctx->d_status, 0, sizeof(unsigned int))) != hipSuccess) return cleanup(e, "hipMemset");
+    if ((e = hipMalloc(&ctx->table, 64 * sizeof(rpmi::GroupEntry))) != hipSuccess) return cleanup(e, "hipMalloc");
+    ctx->table_entries = 64;
     *out = ctx;
     return RP_OK;
 }
@@ -169,6 +183,10 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->split_ws) (void)hipFree(ctx->split_ws);
     if (ctx->split_counters) (void)hipFree(ctx->split_counters);
+    if (ctx->table) (void)hipFree(ctx->table);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph_table) (void)hipFree(ctx->graph_table);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RP_OK;
 }
@@ -322,40 +340,48 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
             a.counters = ctx->split_counters;
             a.partial = static_cast<float*>(ctx->split_ws);
         }
-        RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
+        RP_HIP(ctx, rpmi::launch_project_split_f16(a, ctx->table, s));
     } else {
         RP_HIP(ctx, rpmi::launch_project_f32(a, s));
     }
     return RP_OK;
 }
 
-// Several split-FP16 projections in one grouped launch (every problem on the
-// 16-byte path, all with r <= 128 or all with r > 128); the contraction split
-// of each problem is planned for its share of the compute units, in
-// proportion to its A bytes.  Returns RP_ERR_UNSUPPORTED (nothing launched)
-// when the problems do not qualify; the caller then launches them one by one.
-rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const* A, const int64_t* r,
-                                    const rpmi::PackedOmega* pk, float* const* Y, const int64_t* ldy,
-                                    hipStream_t s) {
-    if (count <= 0 || count > rpmi::kMaxGroup) return RP_ERR_UNSUPPORTED;
-    const bool narrow = r[0] <= 128;
-    rpmi::GroupArgs ga;
-    ga.count = count;
+// Grow the device table of grouped projections to `entries` (synchronises
+// the device when it grows).
+rp_status ensure_table(rp_ctx ctx, size_t entries) {
+    if (entries <= ctx->table_entries) return RP_OK;
+    RP_HIP(ctx, hipDeviceSynchronize());
+    RP_HIP(ctx, hipFree(ctx->table));
+    ctx->table = nullptr;
+    ctx->table_entries = 0;
+    const size_t n = (entries + 255) & ~size_t(255);
+    RP_HIP(ctx, hipMalloc(&ctx->table, n * sizeof(rpmi::GroupEntry)));
+    ctx->table_entries = n;
+    return RP_OK;
+}
+
+// Plan a set of split-FP16 projections for one grouped launch per column
+// width: each problem's contraction split is planned for its share of the
+// compute units (in proportion to its A bytes, times `cu_scale`), the split-K
+// counters and partials are laid out in the context buffers, and the table
+// entries (narrow ones first) are returned with the block count of each
+// width.  Problems must be on the 16-byte path (split_vector_ok).
+struct GroupPlan {
+    std::vector<rpmi::GroupEntry> entries;
+    int narrow_count = 0;
+    int64_t narrow_blocks = 0, wide_blocks = 0;
+};
+
+rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, double cu_scale, GroupPlan* out) {
     double total = 0;
-    for (int g = 0; g < count; ++g) total += (double)A[g]->rows * A[g]->cols;
+    for (const auto& a : probs) total += (double)a.m * a.n;
     const int cus = ctx->num_cus > 0 ? ctx->num_cus : 256;
+    std::vector<rpmi::SplitPlan> plans(probs.size());
     size_t counter_bytes = 0, partial_bytes = 0;
-    rpmi::SplitPlan plans[rpmi::kMaxGroup];
-    for (int g = 0; g < count; ++g) {
-        if ((r[g] <= 128) != narrow || A[g]->rows == 0 || A[g]->cols == 0 || r[g] == 0) return RP_ERR_UNSUPPORTED;
-        rpmi::ProjArgs& a = ga.prob[g];
-        a.A = A[g]->ptr; a.m = A[g]->rows; a.n = A[g]->cols;
-        a.s_row = A[g]->s_row; a.k_inner = A[g]->k_inner; a.s_k_outer = A[g]->s_k_outer;
-        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
-        a.Y = Y[g]; a.ldy = ldy[g]; a.r = r[g];
-        a.status = ctx->d_status;
-        if (!rpmi::split_vector_ok(a)) return RP_ERR_UNSUPPORTED;
-        int share = (int)(cus * ((double)a.m * a.n / total) + 0.5);
+    for (size_t g = 0; g < probs.size(); ++g) {
+        const auto& a = probs[g];
+        const int share = (int)(cus * cu_scale * ((double)a.m * a.n / total) + 0.5);
         plans[g] = rpmi::plan_split_f16(a.m, a.n, a.r, share > 0 ? share : 1);
         counter_bytes += (plans[g].counter_bytes + 255) & ~size_t(255);
         partial_bytes += (plans[g].partial_bytes + 255) & ~size_t(255);
@@ -364,20 +390,77 @@ rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const*
     if (st != RP_OK) return st;
     char* cbase = reinterpret_cast<char*>(ctx->split_counters);
     char* pbase = static_cast<char*>(ctx->split_ws);
-    ga.start[0] = 0;
-    for (int g = 0; g < count; ++g) {
-        rpmi::ProjArgs& a = ga.prob[g];
-        a.ksplit = plans[g].ksplit;
-        a.counters = a.ksplit > 1 ? reinterpret_cast<unsigned int*>(cbase) : nullptr;
-        a.partial = a.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
-        cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
-        pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
-        ga.tiles_m[g] = (a.m + rpmi::split_group_tile_m(a.r) - 1) / rpmi::split_group_tile_m(a.r);
-        ga.tiles_n[g] = (a.r + rpmi::split_group_tile_n(a.r) - 1) / rpmi::split_group_tile_n(a.r);
-        ga.start[g + 1] = ga.start[g] + ga.tiles_m[g] * ga.tiles_n[g] * a.ksplit;
+    out->entries.clear();
+    out->narrow_count = 0;
+    out->narrow_blocks = out->wide_blocks = 0;
+    for (int pass = 0; pass < 2; ++pass) {           // narrow problems, then wide ones
+        int64_t start = 0;
+        for (size_t g = 0; g < probs.size(); ++g) {
+            const bool narrow = probs[g].r <= 128;
+            if (narrow != (pass == 0)) continue;
+            rpmi::GroupEntry e;
+            e.p = probs[g];
+            e.p.ksplit = plans[g].ksplit;
+            e.p.counters = e.p.ksplit > 1 ? reinterpret_cast<unsigned int*>(cbase) : nullptr;
+            e.p.partial = e.p.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
+            cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
+            pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
+            const int64_t bm = rpmi::split_group_tile_m(e.p.r), bn = rpmi::split_group_tile_n(e.p.r);
+            e.tiles_m = (e.p.m + bm - 1) / bm;
+            e.tiles_n = (e.p.r + bn - 1) / bn;
+            e.start = start;
+            start += e.tiles_m * e.tiles_n * e.p.ksplit;
+            out->entries.push_back(e);
+        }
+        if (pass == 0) {
+            out->narrow_count = (int)out->entries.size();
+            out->narrow_blocks = start;
+        } else {
+            out->wide_blocks = start;
+        }
     }
-    RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ga, narrow, s));
     return RP_OK;
+}
+
+// Write a planned group to `table` (device, stream-ordered) and launch it:
+// one launch per column width present.
+rp_status launch_group(rp_ctx ctx, const GroupPlan& gp, rpmi::GroupEntry* table, hipStream_t s) {
+    if (gp.entries.empty()) return RP_OK;
+    RP_HIP(ctx, hipMemcpyAsync(table, gp.entries.data(), gp.entries.size() * sizeof(rpmi::GroupEntry),
+                               hipMemcpyHostToDevice, s));
+    const int wide_count = (int)gp.entries.size() - gp.narrow_count;
+    if (gp.narrow_count > 0)
+        RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table, gp.narrow_count, gp.narrow_blocks, true, s));
+    if (wide_count > 0)
+        RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table + gp.narrow_count, wide_count, gp.wide_blocks,
+                                                           false, s));
+    return RP_OK;
+}
+
+// Several split-FP16 projections in grouped launches.  Returns
+// RP_ERR_UNSUPPORTED (nothing launched) when a problem is not on the 16-byte
+// path; the caller then launches them one by one.
+rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const* A, const int64_t* r,
+                                    const rpmi::PackedOmega* pk, float* const* Y, const int64_t* ldy,
+                                    hipStream_t s) {
+    if (count <= 0) return RP_ERR_UNSUPPORTED;
+    std::vector<rpmi::ProjArgs> probs(count);
+    for (int g = 0; g < count; ++g) {
+        if (A[g]->rows == 0 || A[g]->cols == 0 || r[g] == 0) return RP_ERR_UNSUPPORTED;
+        rpmi::ProjArgs& a = probs[g];
+        a.A = A[g]->ptr; a.m = A[g]->rows; a.n = A[g]->cols;
+        a.s_row = A[g]->s_row; a.k_inner = A[g]->k_inner; a.s_k_outer = A[g]->s_k_outer;
+        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
+        a.Y = Y[g]; a.ldy = ldy[g]; a.r = r[g];
+        a.status = ctx->d_status;
+        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+        if (!rpmi::split_vector_ok(a)) return RP_ERR_UNSUPPORTED;
+    }
+    GroupPlan gp;
+    rp_status st = plan_group(ctx, probs, 1.0, &gp);
+    if (st != RP_OK) return st;
+    if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
+    return launch_group(ctx, gp, ctx->table, s);
 }
 
 }  // namespace
@@ -504,6 +587,111 @@ rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy,
     return RP_OK;
 }
 
+// Scratch of one RSVD after its projection (sized for m x n, rank k, p
+// columns): Q, Z, W, the FP64 CholeskyQR2 and Jacobi buffers, and W in FP32
+// fragment order for the power scheme's projections.
+struct RsvdScratch {
+    int64_t m = 0, n = 0, k = 0, p = 0;
+    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, bytes;
+    float *Q, *Z, *W;
+    double *Qd, *G, *X, *L1, *MW, *MV, *sig, *Ur, *Vr;
+    int* ord;
+    rpmi::PackedOmega pkw;
+
+    // reserve the scratch in `ar` (one block); returns its offset
+    size_t layout(Arena& outer, int64_t m_, int64_t n_, int64_t k_, int64_t p_) {
+        m = m_; n = n_; k = k_; p = p_;
+        Arena ar;
+        const int64_t mx = m > n ? m : n;
+        o_q = ar.take((size_t)m * p * 4);
+        o_z = ar.take((size_t)n * p * 4);
+        o_w = ar.take((size_t)n * p * 4);
+        o_qd = ar.take((size_t)mx * p * 8);
+        o_g = ar.take((size_t)p * p * 8);
+        o_x = ar.take((size_t)p * p * 8);
+        o_l1 = ar.take((size_t)p * p * 8);
+        o_mw = ar.take((size_t)p * p * 8);
+        o_mv = ar.take((size_t)p * p * 8);
+        o_sig = ar.take((size_t)p * 8);
+        o_ord = ar.take((size_t)p * 4);
+        o_ur = ar.take((size_t)p * k * 8);
+        o_vr = ar.take((size_t)p * k * 8);
+        pkw = packed_geometry(n, p, RP_ALGO_F32, nullptr);
+        o_pkw = ar.take(packed_bytes(pkw, RP_ALGO_F32));
+        bytes = ar.used;
+        return outer.take(bytes);
+    }
+    void bind(char* b) {
+        Q = reinterpret_cast<float*>(b + o_q);
+        Z = reinterpret_cast<float*>(b + o_z);
+        W = reinterpret_cast<float*>(b + o_w);
+        Qd = reinterpret_cast<double*>(b + o_qd);
+        G = reinterpret_cast<double*>(b + o_g);
+        X = reinterpret_cast<double*>(b + o_x);
+        L1 = reinterpret_cast<double*>(b + o_l1);
+        MW = reinterpret_cast<double*>(b + o_mw);
+        MV = reinterpret_cast<double*>(b + o_mv);
+        sig = reinterpret_cast<double*>(b + o_sig);
+        ord = reinterpret_cast<int*>(b + o_ord);
+        Ur = reinterpret_cast<double*>(b + o_ur);
+        Vr = reinterpret_cast<double*>(b + o_vr);
+        pkw.data = b + o_pkw;
+    }
+};
+
+rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) {
+    const int64_t p = q.k + q.oversample;
+    if (q.m <= 0 || q.n <= 0 || q.k <= 0 || q.oversample < 0 || power_iters < 0)
+        return fail(ctx, RP_ERR_INVALID_ARG, "invalid sizes (m %lld, n %lld, k %lld, s %lld, q %d)", (long long)q.m,
+                    (long long)q.n, (long long)q.k, (long long)q.oversample, (int)power_iters);
+    if (p > q.m || p > q.n || p > 1024)
+        return fail(ctx, RP_ERR_INVALID_ARG, "k + oversample = %lld must be <= min(m, n) and <= 1024", (long long)p);
+    if (!q.A || !q.U || !q.S || !q.VT) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    if (q.lda < q.n || q.ldu < q.k || q.ldvt < q.n) return fail(ctx, RP_ERR_INVALID_ARG, "leading dimension too small");
+    const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+    rp_status st;
+    if (!proj_layout_ok(ctx, &dA, &st)) return st;
+    return RP_OK;
+}
+
+// Algorithm 1 after Y = A Omega: the power scheme (re-orthonormalised), then
+// Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B, SVD of R_B^T, U and V^T.  Launches
+// kernels and device-to-device copies only (capturable in a graph).
+rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
+                                int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
+    rp_status st;
+    const int64_t m = q.m, n = q.n, k = q.k, lda = q.lda;
+    const float* A = q.A;
+    for (int32_t t = 0; t < power_iters; ++t) {
+        if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+        // Z = A^T Q (n x p)
+        RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
+        if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+        // Y = A W (FP32 x FP32): the FP32 projection kernel with W in fragment order
+        RP_HIP(ctx, rpmi::launch_pack_omega(w.W, true, n, p, p, w.pkw, true, s));
+        if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
+    }
+    // Algorithm 1 line 2: Q = QR(Y)
+    if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+    // line 3: B^T = A^T Q (n x p)
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
+    // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
+    if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+    // SVD of R_B^T = U_r S V_r^T: then B = U_r S (Q_B V_r)^T
+    RP_HIP(ctx, rpmi::jacobi_svd(w.MW, w.MV, (int)p, 40, 1e-14, ctx->d_status, s));
+    RP_HIP(ctx, rpmi::svd_finish(w.MW, w.MV, (int)p, (int)k, w.sig, w.ord, w.Ur, w.Vr, s));
+    RP_HIP(ctx, hipMemcpyAsync(q.S, w.sig, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // line 5: U = Q U_r[:, :k] (m x k); V^T = (Q_B V_r[:, :k])^T (k x n)
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, w.Q, p, 1, w.Ur, k, 1, 0.0, q.U, q.ldu, 1, s)));
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, w.W, p, 1, w.Vr, k, 1, 0.0, q.VT, 1, q.ldvt, s)));
+    return RP_OK;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -514,89 +702,281 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
-    const int64_t p = k + oversample;
-    if (m <= 0 || n <= 0 || k <= 0 || oversample < 0 || power_iters < 0)
-        return fail(ctx, RP_ERR_INVALID_ARG, "invalid sizes (m %lld, n %lld, k %lld, s %lld, q %d)", (long long)m,
-                    (long long)n, (long long)k, (long long)oversample, (int)power_iters);
-    if (p > m || p > n || p > 1024)
-        return fail(ctx, RP_ERR_INVALID_ARG, "k + oversample = %lld must be <= min(m, n) and <= 1024", (long long)p);
-    if (!A || !U || !S || !VT) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
-    if (lda < n || ldu < k || ldvt < n) return fail(ctx, RP_ERR_INVALID_ARG, "leading dimension too small");
+    const rp_rsvd_problem prob{m, n, A, lda, k, oversample, U, ldu, S, VT, ldvt};
+    if ((st = rsvd_check(ctx, prob, power_iters)) != RP_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     RP_HIP(ctx, hipSetDevice(ctx->device));
-
-    rp_desc dA{A, m, n, lda, n, 1, 0};
-    if (!proj_layout_ok(ctx, &dA, &st)) return st;
-
-    // workspace layout
+    const int64_t p = k + oversample;
+    const rp_desc dA{A, m, n, lda, n, 1, 0};
     Arena ar;
     rpmi::PackedOmega pk = packed_geometry(n, p, algo, nullptr);
     const size_t o_pk = ar.take(packed_bytes(pk, algo));
-    const rpmi::PackedOmega pkw_geom = packed_geometry(n, p, RP_ALGO_F32, nullptr);   // W for Y = A W
-    const size_t o_pkw = ar.take(packed_bytes(pkw_geom, RP_ALGO_F32));
-    const size_t o_raw = ar.take(algo == RP_ALGO_F32 ? (size_t)n * p * 4 : 0);       // raw Omega (FP32 path)
-    const int64_t mx = m > n ? m : n;
-    const size_t o_y = ar.take((size_t)m * p * 4);        // Y (m x p)
-    const size_t o_q = ar.take((size_t)m * p * 4);        // Q (m x p)
-    const size_t o_z = ar.take((size_t)n * p * 4);        // Z / B^T (n x p)
-    const size_t o_w = ar.take((size_t)n * p * 4);        // W / Q_B (n x p)
-    const size_t o_qd = ar.take((size_t)mx * p * 8);      // FP64 Q of the first CholeskyQR pass
-    const size_t o_g = ar.take((size_t)p * p * 8);
-    const size_t o_x = ar.take((size_t)p * p * 8);
-    const size_t o_l1 = ar.take((size_t)p * p * 8);
-    const size_t o_mw = ar.take((size_t)p * p * 8);       // R_B^T -> Jacobi W
-    const size_t o_mv = ar.take((size_t)p * p * 8);       // Jacobi V
-    const size_t o_sig = ar.take((size_t)p * 8);
-    const size_t o_ord = ar.take((size_t)p * 4);
-    const size_t o_ur = ar.take((size_t)p * k * 8);
-    const size_t o_vr = ar.take((size_t)p * k * 8);
+    const size_t o_raw = ar.take(algo == RP_ALGO_F32 ? (size_t)n * p * 4 : 0);   // raw Omega (FP32 path)
+    const size_t o_y = ar.take((size_t)m * p * 4);
+    RsvdScratch w;
+    const size_t o_w = w.layout(ar, m, n, k, p);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     char* base = static_cast<char*>(ctx->ws);
     pk.data = base + o_pk;
-    rpmi::PackedOmega pkw = pkw_geom;
-    pkw.data = base + o_pkw;
+    w.bind(base + o_w);
     float* Y = reinterpret_cast<float*>(base + o_y);
-    float* Q = reinterpret_cast<float*>(base + o_q);
-    float* Z = reinterpret_cast<float*>(base + o_z);
-    float* W = reinterpret_cast<float*>(base + o_w);
-    double* Qd = reinterpret_cast<double*>(base + o_qd);
-    double* G = reinterpret_cast<double*>(base + o_g);
-    double* X = reinterpret_cast<double*>(base + o_x);
-    double* L1 = reinterpret_cast<double*>(base + o_l1);
-    double* MW = reinterpret_cast<double*>(base + o_mw);
-    double* MV = reinterpret_cast<double*>(base + o_mv);
-    double* sig = reinterpret_cast<double*>(base + o_sig);
-    int* ord = reinterpret_cast<int*>(base + o_ord);
-    double* Ur = reinterpret_cast<double*>(base + o_ur);
-    double* Vr = reinterpret_cast<double*>(base + o_vr);
-
     // Algorithm 1 line 1: Y = A Omega
     if ((st = fill_packed(ctx, seed, 0, nullptr, 0, omega_type, n, p, algo, pk, base + o_raw, s)) != RP_OK) return st;
     if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s)) != RP_OK) return st;
-    // power scheme, re-orthonormalised
-    for (int32_t t = 0; t < power_iters; ++t) {
-        if ((st = cholqr2(ctx, m, p, Y, p, Q, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
-        // Z = A^T Q (n x p)
-        RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
-        if ((st = cholqr2(ctx, n, p, Z, p, W, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
-        // Y = A W (FP32 x FP32): the FP32 projection kernel with W (n x p) in
-        // fragment order
-        RP_HIP(ctx, rpmi::launch_pack_omega(W, true, n, p, p, pkw, true, s));
-        if ((st = launch_projection(ctx, &dA, p, pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
+    return rsvd_after_projection(ctx, dA, prob, p, power_iters, Y, w, s);
+}
+
+rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem* probs, rp_omega_t omega_type,
+                             void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
+    if (omega_type != RP_OMEGA_F16) return fail(ctx, RP_ERR_UNSUPPORTED, "grouped projections take an FP16 Omega");
+    rp_status st;
+    for (int32_t g = 0; g < count; ++g) {
+        const rp_project_problem& q = probs[g];
+        if (!desc_ok(ctx, &q.A, &st)) return st;
+        if (q.r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "problem %d: negative r", (int)g);
+        if (q.A.rows > 0 && q.r > 0) {
+            if (!q.Y || q.ldy < q.r) return fail(ctx, RP_ERR_INVALID_ARG, "problem %d: bad Y", (int)g);
+            if (q.A.cols > 0 && !proj_layout_ok(ctx, &q.A, &st)) return st;
+        }
     }
-    // Algorithm 1 line 2: Q = QR(Y)
-    if ((st = cholqr2(ctx, m, p, Y, p, Q, p, nullptr, Qd, G, X, L1, s)) != RP_OK) return st;
-    // line 3: B^T = A^T Q (n x p)
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
-    // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
-    if ((st = cholqr2(ctx, n, p, Z, p, W, p, MW, Qd, G, X, L1, s)) != RP_OK) return st;
-    // SVD of R_B^T = U_r S V_r^T: then B = U_r S (Q_B V_r)^T
-    RP_HIP(ctx, rpmi::jacobi_svd(MW, MV, (int)p, 40, 1e-14, ctx->d_status, s));
-    RP_HIP(ctx, rpmi::svd_finish(MW, MV, (int)p, (int)k, sig, ord, Ur, Vr, s));
-    RP_HIP(ctx, hipMemcpyAsync(S, sig, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // line 5: U = Q U_r[:, :k] (m x k); V^T = (Q_B V_r[:, :k])^T (k x n)
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, Q, p, 1, Ur, k, 1, 0.0, U, ldu, 1, s)));
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, W, p, 1, Vr, k, 1, 0.0, VT, 1, ldvt, s)));
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    Arena ar;
+    std::vector<size_t> off(count);
+    std::vector<rpmi::PackedOmega> pk(count);
+    for (int32_t g = 0; g < count; ++g) {
+        pk[g] = packed_geometry(probs[g].A.cols, probs[g].r, RP_ALGO_SPLIT_F16, nullptr);
+        off[g] = ar.take(packed_bytes(pk[g], RP_ALGO_SPLIT_F16));
+    }
+    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
+    std::vector<rpmi::ProjArgs> grouped;
+    for (int32_t g = 0; g < count; ++g) {
+        const rp_project_problem& q = probs[g];
+        if (q.A.rows == 0 || q.r == 0) continue;
+        if (q.A.cols == 0) {
+            RP_HIP(ctx, rpmi::launch_fill_f32(q.Y, q.A.rows, q.r, q.ldy, 0.0f, s));
+            continue;
+        }
+        pk[g].data = static_cast<char*>(ctx->ws) + off[g];
+        RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), q.seed, q.stream_id, q.A.cols, q.r, pk[g], s));
+        rpmi::ProjArgs a;
+        a.A = q.A.ptr; a.m = q.A.rows; a.n = q.A.cols;
+        a.s_row = q.A.s_row; a.k_inner = q.A.k_inner; a.s_k_outer = q.A.s_k_outer;
+        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
+        a.Y = q.Y; a.ldy = q.ldy; a.r = q.r;
+        a.status = ctx->d_status;
+        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+        if (rpmi::split_vector_ok(a)) {
+            grouped.push_back(a);
+        } else if ((st = launch_projection(ctx, &q.A, q.r, pk[g], RP_ALGO_SPLIT_F16, q.Y, q.ldy, s)) != RP_OK) {
+            return st;
+        }
+    }
+    if (grouped.empty()) return RP_OK;
+    GroupPlan gp;
+    if ((st = plan_group(ctx, grouped, 1.0, &gp)) != RP_OK) return st;
+    if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
+    return launch_group(ctx, gp, ctx->table, s);
+}
+
+rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, int32_t power_iters,
+                       uint64_t seed, rp_omega_t omega_type, void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
+    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_F32)
+        return fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)omega_type);
+    const rp_algo_t algo = omega_type == RP_OMEGA_F16 ? RP_ALGO_SPLIT_F16 : RP_ALGO_F32;
+    rp_status st;
+    for (int32_t g = 0; g < count; ++g)
+        if ((st = rsvd_check(ctx, probs[g], power_iters)) != RP_OK) return st;
+    if (count == 0) return RP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+
+    // workspace: per problem its packed Omega and Y; one scratch block sized
+    // for the largest problem, shared (the per-problem stages run in order)
+    Arena ar;
+    std::vector<size_t> o_pk(count), o_y(count);
+    std::vector<rpmi::PackedOmega> pk(count);
+    int64_t mm = 0, mn = 0, mk = 0, mp = 0;
+    size_t raw = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const rp_rsvd_problem& q = probs[g];
+        const int64_t p = q.k + q.oversample;
+        pk[g] = packed_geometry(q.n, p, algo, nullptr);
+        o_pk[g] = ar.take(packed_bytes(pk[g], algo));
+        o_y[g] = ar.take((size_t)q.m * p * 4);
+        mm = q.m > mm ? q.m : mm; mn = q.n > mn ? q.n : mn; mk = q.k > mk ? q.k : mk; mp = p > mp ? p : mp;
+        if (algo == RP_ALGO_F32) raw = (size_t)q.n * p * 4 > raw ? (size_t)q.n * p * 4 : raw;
+    }
+    const size_t o_raw = ar.take(raw);
+    RsvdScratch w;
+    const size_t o_w = w.layout(ar, mm, mn, mk, mp);
+    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
+    char* base = static_cast<char*>(ctx->ws);
+    for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
+    w.bind(base + o_w);
+
+    // projections of the 16-byte-path problems go out grouped
+    std::vector<rpmi::ProjArgs> grouped;
+    std::vector<int> single;
+    uint64_t sig = mix(0, (uint64_t)count);
+    for (int32_t g = 0; g < count; ++g) {
+        const rp_rsvd_problem& q = probs[g];
+        rpmi::ProjArgs a;
+        a.A = q.A; a.m = q.m; a.n = q.n; a.s_row = q.lda; a.k_inner = q.n; a.s_k_outer = 0;
+        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
+        a.Y = reinterpret_cast<float*>(base + o_y[g]); a.ldy = q.k + q.oversample; a.r = q.k + q.oversample;
+        a.status = ctx->d_status;
+        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+        if (algo == RP_ALGO_SPLIT_F16 && rpmi::split_vector_ok(a)) grouped.push_back(a);
+        else single.push_back(g);
+        sig = mix(mix(mix(sig, (uint64_t)q.m), (uint64_t)q.n), (uint64_t)a.r);
+    }
+
+    // the graph of this exact call: problem set, buffers, options, context buffers
+    auto call_key = [&]() {
+        uint64_t key = mix(sig, seed);
+        key = mix(mix(key, (uint64_t)power_iters), (uint64_t)omega_type);
+        for (int32_t g = 0; g < count; ++g) {
+            const rp_rsvd_problem& q = probs[g];
+            key = mix(mix(mix(key, (uint64_t)(uintptr_t)q.A), (uint64_t)q.lda), (uint64_t)q.k);
+            key = mix(mix(mix(key, (uint64_t)(uintptr_t)q.U), (uint64_t)(uintptr_t)q.S), (uint64_t)(uintptr_t)q.VT);
+            key = mix(mix(mix(key, (uint64_t)q.ldu), (uint64_t)q.ldvt), (uint64_t)q.oversample);
+        }
+        key = mix(mix(key, (uint64_t)(uintptr_t)ctx->ws), (uint64_t)ctx->ws_bytes);
+        key = mix(mix(key, (uint64_t)(uintptr_t)ctx->split_ws), (uint64_t)ctx->split_ws_bytes);
+        return mix(mix(key, (uint64_t)(uintptr_t)ctx->split_counters), (uint64_t)ctx->split_counter_bytes);
+    };
+    if (ctx->graph_exec && call_key() == ctx->graph_key) {
+        RP_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
+        return RP_OK;
+    }
+
+    auto gen_omega = [&](hipStream_t st_) -> rp_status {
+        for (int32_t g = 0; g < count; ++g) {
+            const rp_rsvd_problem& q = probs[g];
+            rp_status r2 = fill_packed(ctx, seed, (uint32_t)g, nullptr, 0, omega_type, q.n, q.k + q.oversample, algo,
+                                       pk[g], base + o_raw, st_);
+            if (r2 != RP_OK) return r2;
+        }
+        return RP_OK;
+    };
+    RP_HIP(ctx, hipStreamSynchronize(s));
+    if (!ctx->cap_stream) RP_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->cap_stream;
+
+    // autotuner: the contraction split of every grouped problem follows its
+    // share of the compute units times a scale; the scale is chosen once per
+    // problem-shape signature by timing the grouped projection
+    GroupPlan gp;
+    if (!grouped.empty()) {
+        auto it = ctx->tuned_scale.find(sig);
+        double best = 1.0;
+        if (it != ctx->tuned_scale.end()) {
+            best = it->second;
+        } else {
+            if ((st = gen_omega(cs)) != RP_OK) return st;
+            hipEvent_t e0, e1;
+            RP_HIP(ctx, hipEventCreate(&e0));
+            RP_HIP(ctx, hipEventCreate(&e1));
+            float best_ms = 1e30f;
+            for (double scale : {0.5, 1.0, 2.0, 4.0}) {
+                if ((st = plan_group(ctx, grouped, scale, &gp)) != RP_OK) return st;
+                if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
+                if ((st = launch_group(ctx, gp, ctx->table, cs)) != RP_OK) return st;   // warm-up
+                RP_HIP(ctx, hipEventRecord(e0, cs));
+                for (int rep = 0; rep < 3; ++rep)
+                    if ((st = launch_group(ctx, gp, ctx->table, cs)) != RP_OK) return st;
+                RP_HIP(ctx, hipEventRecord(e1, cs));
+                RP_HIP(ctx, hipEventSynchronize(e1));
+                float ms = 0;
+                RP_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) { best_ms = ms; best = scale; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            ctx->tuned_scale[sig] = best;
+        }
+        if ((st = plan_group(ctx, grouped, best, &gp)) != RP_OK) return st;
+        if (gp.entries.size() > ctx->graph_table_entries) {
+            if (ctx->graph_table) RP_HIP(ctx, hipFree(ctx->graph_table));
+            ctx->graph_table = nullptr;
+            ctx->graph_table_entries = 0;
+            RP_HIP(ctx, hipMalloc(&ctx->graph_table, gp.entries.size() * sizeof(rpmi::GroupEntry)));
+            ctx->graph_table_entries = gp.entries.size();
+        }
+        RP_HIP(ctx, hipMemcpy(ctx->graph_table, gp.entries.data(), gp.entries.size() * sizeof(rpmi::GroupEntry),
+                              hipMemcpyHostToDevice));
+    }
+    RP_HIP(ctx, hipDeviceSynchronize());
+
+    // capture: Omega generation, the grouped projections, then every
+    // problem's CholeskyQR2 / B / SVD stages
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
+    RP_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    auto body = [&]() -> rp_status {
+        rp_status r2 = gen_omega(cs);
+        if (r2 != RP_OK) return r2;
+        if (!gp.entries.empty()) {
+            const int wide = (int)gp.entries.size() - gp.narrow_count;
+            if (gp.narrow_count > 0)
+                RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ctx->graph_table, gp.narrow_count,
+                                                                   gp.narrow_blocks, true, cs));
+            if (wide > 0)
+                RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ctx->graph_table + gp.narrow_count, wide,
+                                                                   gp.wide_blocks, false, cs));
+        }
+        for (int g : single) {
+            const rp_rsvd_problem& q = probs[g];
+            const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+            const int64_t p = q.k + q.oversample;
+            if (algo == RP_ALGO_SPLIT_F16) {
+                // off the 16-byte path: the general split kernel (no table)
+                rpmi::ProjArgs a;
+                a.A = q.A; a.m = q.m; a.n = q.n; a.s_row = q.lda; a.k_inner = q.n; a.s_k_outer = 0;
+                a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
+                a.Y = reinterpret_cast<float*>(base + o_y[g]); a.ldy = p; a.r = p;
+                a.status = ctx->d_status;
+                a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+                RP_HIP(ctx, rpmi::launch_project_split_f16(a, nullptr, cs));
+            } else if ((r2 = launch_projection(ctx, &dA, p, pk[g], algo, reinterpret_cast<float*>(base + o_y[g]), p,
+                                               cs)) != RP_OK) {
+                return r2;
+            }
+        }
+        for (int32_t g = 0; g < count; ++g) {
+            const rp_rsvd_problem& q = probs[g];
+            const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+            RsvdScratch wg = w;
+            wg.m = q.m; wg.n = q.n; wg.k = q.k; wg.p = q.k + q.oversample;
+            wg.pkw = packed_geometry(q.n, wg.p, RP_ALGO_F32, w.pkw.data);
+            r2 = rsvd_after_projection(ctx, dA, q, q.k + q.oversample, power_iters,
+                                       reinterpret_cast<float*>(base + o_y[g]), wg, cs);
+            if (r2 != RP_OK) return r2;
+        }
+        return RP_OK;
+    };
+    const rp_status body_st = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (body_st != RP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return body_st;
+    }
+    if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ctx, ie, "hipGraphInstantiate");
+    ctx->graph_exec = exec;
+    ctx->graph_key = call_key();
+    RP_HIP(ctx, hipGraphLaunch(exec, s));
     return RP_OK;
 }
 
@@ -712,9 +1092,7 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
             gA[cnt] = dp[i]; gr[cnt] = ranks[i]; gld[cnt] = ldw[i]; gpk[cnt] = pk[i]; gY[cnt] = W[i];
             ++cnt;
         }
-        bool same_width = true;
-        for (int g = 1; g < cnt; ++g) same_width = same_width && ((gr[g] <= 128) == (gr[0] <= 128));
-        if (cnt > 1 && same_width) {
+        if (cnt > 1) {
             st = launch_projection_grouped(ctx, cnt, gA, gr, gpk, gY, gld, s);
             if (st == RP_OK) grouped_done = true;
             else if (st != RP_ERR_UNSUPPORTED) return st;

@@ -54,22 +54,22 @@ struct ProjArgs {
     unsigned int* counters;           // one per output tile, zero between launches
 };
 
-// Several split-FP16 projections in one launch (all on the 16-byte aligned
-// path).  Problem g owns blocks [start[g], start[g+1]): tiles_m x tiles_n
-// output tiles times its contraction split prob[g].ksplit.
-constexpr int kMaxGroup = 8;
-struct GroupArgs {
-    int count;
-    ProjArgs prob[kMaxGroup];
-    int64_t tiles_m[kMaxGroup], tiles_n[kMaxGroup];
-    int64_t start[kMaxGroup + 1];
+// Several split-FP16 projections in one launch (all on the 16-byte path and
+// of one column width: r <= 128 or r > 128).  The problem table lives in
+// device memory; entry g owns blocks [start, start + tiles_m * tiles_n *
+// ksplit), and entries are sorted by start.
+constexpr int kMaxGroup = 8;          // modes of rp_hosvd
+struct GroupEntry {
+    ProjArgs p;
+    int64_t tiles_m, tiles_n;
+    int64_t start;
 };
 int64_t split_group_tile_m(int64_t r);
 int64_t split_group_tile_n(int64_t r);
-// all problems of one grouped launch use the same tile: narrow (r <= 128) or not
-hipError_t launch_project_split_f16_grouped(const GroupArgs& ga, bool narrow, hipStream_t s);
-hipError_t launch_split_group_wide(const GroupArgs& ga, hipStream_t s);     // r > 128
-hipError_t launch_split_group_narrow(const GroupArgs& ga, hipStream_t s);   // r <= 128
+hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
+                                            hipStream_t s);
+hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, hipStream_t s);
+hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, hipStream_t s);
 bool split_vector_ok(const ProjArgs& a);
 
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
@@ -98,7 +98,7 @@ hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
 hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
                              const PackedOmega& dst, bool dst_f32, hipStream_t s);
-hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s);
+hipError_t launch_project_split_f16(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s);
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s);
 hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                              hipStream_t s);

@@ -1,0 +1,119 @@
+"""Grouped projections and batched randomized SVD (the batching pattern for
+many problems of different shapes) against the FP64 oracle on the same
+inputs and the same Omega_j (stream j, bit-identical on both sides)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, dev, host, rp
+from oracle import omega, project, rsvd as orsvd
+
+pytestmark = pytest.mark.gpu
+
+U32, U16 = 2.0 ** -24, 2.0 ** -11
+
+
+def test_project_grouped_elementwise_bound():
+    """Mixed widths (r <= 128 and r > 128), shapes off the 16-byte path (odd
+    n) and an empty problem in one call; every Y within the elementwise bound
+    of the split product (gamma_{n+2}(u32) + u16^2) |A| |Omega|."""
+    shapes = [(300, 4096, 200), (1000, 2048, 64), (65, 777, 17), (512, 8192, 256), (128, 128, 130),
+              (2000, 64, 40), (0, 64, 8)]
+    announce(f"grouped projections {shapes}")
+    rng = np.random.default_rng(3)
+    mats = [rng.standard_normal((m, n)).astype(np.float32) for m, n, _ in shapes]
+    probs = [(dev(a), r, 9, j) for j, (a, (_, _, r)) in enumerate(zip(mats, shapes))]
+    ys = rp().rp_project_grouped(probs)
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, (a, (m, n, r)) in enumerate(zip(mats, shapes)):
+        if m == 0:
+            continue
+        om = omega.omega_f16(9, j, n, r)
+        ref = project.project_f64(a, om)
+        bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, om)
+        y = host(ys[j]).astype(np.float64)
+        assert np.all(np.abs(y - ref) <= bound), (j, m, n, r)
+
+
+def _planted_batch(count, seed, lo, hi, kmin, kmax):
+    """m, n log-uniform in [lo, hi], planted rank k, sigma_i =
+    10^(-3 (i-1)/(k-1)), Haar factors, noiseless; p = k + max(10, ceil(k/4))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for (m, n, k, p) in synth.batched_problem_list(count, seed, lo, hi, kmin, kmax):
+        sig = 10.0 ** (-3.0 * np.arange(k) / (k - 1))
+        out.append((synth.np_planted(m, n, sig, rng), k, p - k, sig))
+    return out
+
+
+@pytest.mark.parametrize("omega_type", ["f16", "f32"])
+def test_rsvd_batched_matches_oracle(omega_type):
+    batch = _planted_batch(10, 55, 64, 700, 4, 24)
+    announce(f"rsvd_batched {omega_type} shapes {[a.shape for a, _, _, _ in batch]}")
+    mats = [dev(a) for a, _, _, _ in batch]
+    ks = [k for _, k, _, _ in batch]
+    ss = [s for _, _, s, _ in batch]
+    outs = rp().rsvd_batched(mats, ks, ss, 0, 13, omega_type)
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    gen = omega.omega_f32 if omega_type == "f32" else omega.omega_f16
+    first = []
+    for j, ((a, k, s, sig), (u, sv, vt)) in enumerate(zip(batch, outs)):
+        sv = host(sv)
+        first.append(sv.copy())
+        _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), gen(13, j, a.shape[1], k + s), k, 0)
+        assert np.abs(sv - sv_o).max() <= 1e-5 * sv_o[0], j
+        assert np.abs(sv - sig).max() <= 1e-5 * sig[0], j        # exact recovery of the planted spectrum
+        u, vt = host(u).astype(np.float64), host(vt).astype(np.float64)
+        rec = (u * sv) @ vt
+        assert np.linalg.norm(rec - a) <= 1e-5 * np.linalg.norm(a), j
+    # a second call with the same tensors replays the captured graph: same bits
+    again = rp().rsvd_batched(mats, ks, ss, 0, 13, omega_type, outputs=outs)
+    for j, (u, sv, vt) in enumerate(again):
+        assert np.array_equal(host(sv), first[j])
+    # the graph reads A afresh: doubling every A doubles every singular value
+    for t in mats:
+        t.mul_(2.0)
+    rp().rsvd_batched(mats, ks, ss, 0, 13, omega_type, outputs=outs)
+    for j, (u, sv, vt) in enumerate(outs):
+        assert np.allclose(host(sv), 2.0 * first[j], rtol=1e-6, atol=0), j
+
+
+def test_rsvd_batched_power_iteration_and_errors():
+    batch = _planted_batch(4, 77, 80, 300, 5, 12)
+    announce("rsvd_batched q=1")
+    mats = [dev(a) for a, _, _, _ in batch]
+    outs = rp().rsvd_batched(mats, [k for _, k, _, _ in batch], [s for _, _, s, _ in batch], 1, 3, "f16")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, ((a, k, s, sig), (_, sv, _)) in enumerate(zip(batch, outs)):
+        _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), omega.omega_f16(3, j, a.shape[1], k + s), k, 1)
+        assert np.abs(host(sv) - sv_o).max() <= 1e-5 * sv_o[0], j
+    assert rp().rsvd_batched([], [], [], 0, 0, "f16") == []
+    with pytest.raises(rp().RpError):
+        rp().rsvd_batched([dev(np.ones((10, 10), np.float32))], [8], [8], 0, 0, "f16")   # p > min(m, n)
+
+
+def test_rsvd_batched_full_size_planted():
+    """256 problems, m, n log-uniform in [512, 8192], planted rank k in
+    [16, 128] with sigma_i = 10^(-3 (i-1)/(k-1)), noiseless, FP16 Omega_j:
+    every singular value recovered (a property that holds at any size)."""
+    import torch
+    shapes = synth.batched_problem_list(256, 105, 512, 8192, 16, 128)
+    announce(f"rsvd_batched 256 problems, total A {sum(m * n for m, n, _, _ in shapes) * 4 / 1e9:.2f} GB")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(105)
+    mats, sigs = [], []
+    for m, n, k, p in shapes:
+        sig = torch.tensor(10.0 ** (-3.0 * np.arange(k) / (k - 1)), device="cuda", dtype=torch.float64)
+        u = synth.torch_haar(m, k, gen, "cuda")
+        v = synth.torch_haar(n, k, gen, "cuda")
+        mats.append(((u * sig) @ v.T).float().contiguous())
+        sigs.append(sig.cpu().numpy())
+    ks = [k for _, _, k, _ in shapes]
+    ss = [p - k for _, _, k, p in shapes]
+    outs = rp().rsvd_batched(mats, ks, ss, 0, 205, "f16")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    worst = max(float(np.abs(host(sv) - sig).max()) for (_, sv, _), sig in zip(outs, sigs))
+    print(f"max |sigma - planted| over 256 problems: {worst:.3e}")
+    assert worst <= 1e-5
