@@ -51,7 +51,10 @@ typedef enum rp_status {
 /* Storage format of Omega (Sec. 3: a Gaussian matrix tolerates a short mantissa). */
 typedef enum rp_omega_t {
     RP_OMEGA_F32 = 0,         /* FP32 Gaussian                                     */
-    RP_OMEGA_F16 = 1          /* FP16 Gaussian, exact sample of RN16(N(0,1))        */
+    RP_OMEGA_F16 = 1,         /* FP16 Gaussian, exact sample of RN16(N(0,1))        */
+    RP_OMEGA_E4M3 = 2         /* FP8 e4m3fn of the FP32 Gaussian, power-of-two
+                                 scale per column (rp_omega_generate_e4m3); the
+                                 projections take Omega8 / s_j, exact in FP16     */
 } rp_omega_t;
 
 /* How Y = A * Omega is computed. */
@@ -199,6 +202,19 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
                int64_t k, int64_t oversample, int32_t power_iters,
                uint64_t seed, rp_omega_t omega_type, rp_algo_t algo,
                float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* stream);
+
+/*
+ * e4m3 Omega (the low-precision storage of Sec. 3 with the OCP FP8 E4M3FN
+ * format of Table 1): for the FP32 Omega w of (seed, stream_id) and every
+ * column j, s_j = 2^floor(log2(448 / max_i |w[i][j]|)) (1 for an empty
+ * column) and Omega8[i][j] = sat448(RNE_e4m3(w[i][j] s_j)), so that
+ * A Omega8[:, j] / s_j approximates A w[:, j].  omega: n x r e4m3fn bytes
+ * (ldo >= r); col_scale: r floats s_j.  Device, caller-owned.  The projection
+ * entry points take RP_OMEGA_E4M3 only for a generated Omega: they use the
+ * values Omega8 / s_j, which are exact in FP16.
+ */
+rp_status rp_omega_generate_e4m3(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64_t n, int64_t r,
+                                 uint8_t* omega, int64_t ldo, float* col_scale, void* stream);
 
 /*
  * One projection of a grouped call: Y = A Omega with Omega (A.cols x r, FP16)

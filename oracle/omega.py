@@ -65,3 +65,60 @@ def omega_f32(seed, stream_id, n, r):
     mag = lower + (upper - lower) * ((f + 0.5) * 2.0 ** -32)
     mag32 = mag.astype(np.float32)
     return np.where(sign == 1, -mag32, mag32).astype(np.float32)
+
+
+# --------------------------------------------------------------------------- e4m3
+# OCP FP8 E4M3FN: sign, 4 exponent bits (bias 7), 3 mantissa bits, no
+# infinities; the code with all exponent and mantissa bits set is NaN, so the
+# largest finite value is 1.75 * 2^8 = 448.  Normal values (e >= 1)
+# (1 + m/8) 2^(e-7); subnormal values (e = 0) (m/8) 2^-6.
+
+def e4m3_decode(codes):
+    """Value of e4m3fn codes (uint8 array) as float64 (NaN for the NaN codes)."""
+    c = np.asarray(codes, dtype=np.uint8).astype(np.int64)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 0xF
+    m = c & 0x7
+    mag = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * 2.0 ** (e - 7))
+    mag = np.where((e == 15) & (m == 7), np.nan, mag)
+    return sign * mag
+
+
+def e4m3_encode_rne(x):
+    """Round float64 values to e4m3fn (round to nearest, ties to an even
+    mantissa), saturating at +-448; returns uint8 codes.  From the format's
+    definition: the quantum is 2^(e-3) for |x| in [2^e, 2^(e+1)), e >= -6,
+    and 2^-9 below 2^-6."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, -6.0)
+    q = 2.0 ** (e - 3)
+    t = a / q                                    # exact: division by a power of two
+    r = np.floor(t)
+    frac = t - r
+    up = (frac > 0.5) | ((frac == 0.5) & (np.fmod(r, 2) == 1))
+    v = np.minimum((r + up) * q, 448.0)          # may carry into the next binade: still exact
+    # encode v (a representable magnitude)
+    ve = np.floor(np.log2(np.where(v > 0, v, 1.0)))
+    normal = v >= 2.0 ** -6
+    exp_field = np.where(normal, ve + 7, 0).astype(np.int64)
+    man = np.where(normal, v / 2.0 ** ve * 8 - 8, v / 2.0 ** -9).astype(np.int64)
+    code = (exp_field << 3) | man
+    code = np.where(v == 0, 0, code)
+    return (code | np.where(np.signbit(x) & (v > 0), 0x80, 0)).astype(np.uint8)
+
+
+def omega_e4m3(seed, stream_id, n, r):
+    """The e4m3 Omega with a power-of-two scale per column:
+        s_j = 2^floor(log2(448 / max_i |Omega32[i, j]|)),
+        Omega8[i, j] = sat448(RNE_e4m3(Omega32[i, j] * s_j)),
+    so that Y[:, j] = (A Omega8[:, j]) / s_j.  Returns (codes uint8 n x r,
+    scale float64 r, value float64 n x r = Omega8 / s_j).  The quotient
+    448 / max is one FP64 division; its exponent is taken exactly (frexp)."""
+    w32 = omega_f32(seed, stream_id, n, r).astype(np.float64)
+    cmax = np.abs(w32).max(axis=0) if n > 0 else np.zeros(r)
+    mant, ex = np.frexp(448.0 / np.where(cmax > 0, cmax, 1.0))
+    scale = np.where(cmax > 0, np.ldexp(1.0, ex - 1), 1.0)
+    codes = e4m3_encode_rne(w32 * scale[None, :])
+    return codes, scale, e4m3_decode(codes) / scale[None, :]

@@ -23,10 +23,11 @@ RP_ERR_HIP = 7
 
 RP_OMEGA_F32 = 0
 RP_OMEGA_F16 = 1
+RP_OMEGA_E4M3 = 2
 RP_ALGO_F32 = 0
 RP_ALGO_SPLIT_F16 = 1
 
-OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16}
+OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16, "e4m3": RP_OMEGA_E4M3}
 ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16}
 
 
@@ -80,6 +81,7 @@ def lib():
         "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, vp, i64, vp, vp, i64, vp],
         "rp_hosvd": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
         "rp_project_grouped": [vp, i32, vp, i32, vp],
+        "rp_omega_generate_e4m3": [vp, u64, u32, i64, i64, vp, i64, vp, vp],
         "rsvd_batched": [vp, i32, vp, i32, u64, i32, vp],
     }
     for name, args in sig.items():
@@ -274,6 +276,18 @@ def rp_hosvd(x, ranks, seed=0, omega_type="f16", algo="split_f16", ctx=None):
     _check(ctx.handle, lib().rp_hosvd(ctx.handle, nd, dims_c, _ptr(x), ranks_c, seed, OMEGA_TYPES[omega_type],
                                       ALGOS[algo], _ptr(core), fac_c, _stream()))
     return core, factors
+
+
+def rp_omega_generate_e4m3(n, r, seed=0, stream_id=0, ctx=None):
+    """e4m3 Omega: (codes uint8 n x r, column scales float32 r)."""
+    import torch
+    ctx = ctx or default_context()
+    dev = f"cuda:{ctx.device}"
+    codes = torch.empty((n, r), dtype=torch.uint8, device=dev)
+    scale = torch.empty((r,), dtype=torch.float32, device=dev)
+    _check(ctx.handle, lib().rp_omega_generate_e4m3(ctx.handle, seed, stream_id, n, r, _ptr(codes), max(r, 1),
+                                                    _ptr(scale), _stream()))
+    return codes, scale
 
 
 def rp_project_grouped(problems, omega_type="f16", ctx=None):

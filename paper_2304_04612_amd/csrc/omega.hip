@@ -193,6 +193,91 @@ int grid_for(int64_t total, int block) {
     return (int)(g < 1 ? 1 : g);
 }
 
+// ---------------------------------------------------------------- e4m3 Omega
+// Per column j: s_j = 2^floor(log2(448 / max_i |w[i][j]|)) from the FP32
+// Omega w; Omega8 = sat448(RNE_e4m3fn(w s_j)); the FP16 value Omega8 / s_j is
+// exact (at most 4 significant bits, smallest step 2^-9 / s_j >= 2^-24).
+__global__ void colmax_init_kernel(unsigned int* cmax, int64_t r, float* scale_one) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < r; j += (int64_t)gridDim.x * blockDim.x) {
+        cmax[j] = 0u;
+        if (scale_one) scale_one[j] = 1.0f;      // an empty column keeps scale 1
+    }
+}
+
+// max |w| per column as the bit pattern of a non-negative float (the order of
+// non-negative floats is the order of their patterns)
+__global__ void colmax_kernel(const float* w, int64_t n, int64_t r, int64_t ldw, unsigned int* cmax) {
+    const int64_t total = n * r;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / r, j = q - i * r;
+        atomicMax(&cmax[j], __float_as_uint(fabsf(w[i * ldw + j])));
+    }
+}
+
+__device__ __forceinline__ double e4m3_scale(unsigned int cmax_bits) {
+    const float c = __uint_as_float(cmax_bits);
+    if (c == 0.0f) return 1.0;
+    int ex;
+    (void)frexp(448.0 / (double)c, &ex);          // 448 / c = f 2^ex, f in [1/2, 1)
+    return ldexp(1.0, ex - 1);
+}
+
+__global__ void e4m3_quant_kernel(const float* w, int64_t n, int64_t r, int64_t ldw, const unsigned int* cmax,
+                                  uint8_t* codes, int64_t ldc, uint16_t* f16, int64_t ldf, float* scale_out) {
+    const int64_t total = n * r;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / r, j = q - i * r;
+        const double sc = e4m3_scale(cmax[j]);
+        const double x = (double)w[i * ldw + j] * sc;             // exact: power-of-two scaling
+        const double a = fabs(x);
+        double v = 0.0;
+        if (a > 0.0) {
+            const int e = ilogb(a) > -6 ? ilogb(a) : -6;
+            const double qu = ldexp(1.0, e - 3);
+            v = rint(a / qu) * qu;                                 // a / qu exact; rint is ties-to-even
+            v = v > 448.0 ? 448.0 : v;
+        }
+        if (codes) {
+            unsigned int code = 0;
+            if (v > 0.0) {
+                if (v >= 0x1p-6) {
+                    const int ve = ilogb(v);
+                    code = (unsigned)((ve + 7) << 3) | (unsigned)(ldexp(v, -ve) * 8.0 - 8.0);
+                } else {
+                    code = (unsigned)(v * 512.0);
+                }
+                if (x < 0.0) code |= 0x80u;
+            }
+            codes[i * ldc + j] = (uint8_t)code;
+        }
+        if (f16) {
+            const double val = (x < 0.0 ? -v : v) / sc;
+            f16[i * ldf + j] = v > 0.0 ? __builtin_bit_cast(uint16_t, (_Float16)(float)val) : (uint16_t)0;
+        }
+        if (scale_out && i == 0) scale_out[j] = (float)sc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_omega_e4m3(const OmegaTables& t, uint64_t seed, uint32_t stream_id, int64_t n, int64_t r,
+                             float* w32, unsigned int* cmax, uint8_t* codes, int64_t ldc, uint16_t* f16, int64_t ldf,
+                             float* scale, hipStream_t s) {
+    if (r == 0) return hipSuccess;
+    hipError_t e = launch_omega_rowmajor(t, seed, stream_id, n, r, true, w32, r, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colmax_init_kernel, dim3(grid_for(r, 256)), dim3(256), 0, s, cmax, r,
+                       n == 0 ? scale : (float*)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(colmax_kernel, dim3(grid_for(n * r, 256)), dim3(256), 0, s, w32, n, r, r, cmax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(e4m3_quant_kernel, dim3(grid_for(n * r, 256)), dim3(256), 0, s, w32, n, r, r, cmax, codes, ldc,
+                       f16, ldf, scale);
+    return hipGetLastError();
+}
+
+namespace {
 }  // namespace
 
 hipError_t launch_omega_rowmajor(const OmegaTables& t, uint64_t seed, uint32_t stream_id,

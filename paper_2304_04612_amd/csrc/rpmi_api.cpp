@@ -195,6 +195,8 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64
                             rp_omega_t type, void* omega, int64_t ldo, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     if (n < 0 || r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative size (n %lld, r %lld)", (long long)n, (long long)r);
+    if (type == RP_OMEGA_E4M3)
+        return fail(ctx, RP_ERR_INVALID_ARG, "the e4m3 Omega comes with column scales: use rp_omega_generate_e4m3");
     if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32)
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)type);
     if (n == 0 || r == 0) return RP_OK;
@@ -203,6 +205,24 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64
     RP_HIP(ctx, hipSetDevice(ctx->device));
     RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, type == RP_OMEGA_F32,
                                             omega, ldo, (hipStream_t)stream));
+    return RP_OK;
+}
+
+rp_status rp_omega_generate_e4m3(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64_t n, int64_t r,
+                                 uint8_t* omega, int64_t ldo, float* col_scale, void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 0 || r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative size (n %lld, r %lld)", (long long)n, (long long)r);
+    if (r == 0) return RP_OK;
+    if (!col_scale || (n > 0 && !omega)) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    if (n > 0 && ldo < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldo %lld < r %lld", (long long)ldo, (long long)r);
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    rp_status st;
+    const size_t w_bytes = ((size_t)n * r * 4 + 255) & ~size_t(255);
+    if ((st = ensure_workspace(ctx, w_bytes + (size_t)r * 4)) != RP_OK) return st;
+    float* w32 = static_cast<float*>(ctx->ws);
+    unsigned int* cmax = reinterpret_cast<unsigned int*>(static_cast<char*>(ctx->ws) + w_bytes);
+    RP_HIP(ctx, rpmi::launch_omega_e4m3(tables(ctx), seed, stream_id, n, r, w32, cmax, omega, ldo, nullptr, 0, col_scale,
+                                        (hipStream_t)stream));
     return RP_OK;
 }
 
@@ -251,7 +271,7 @@ size_t packed_bytes(const rpmi::PackedOmega& pk, rp_algo_t algo) {
 }
 
 bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
-    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32) {
+    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32 && type != RP_OMEGA_E4M3) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)type);
         return false;
     }
@@ -259,11 +279,18 @@ bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "unknown algorithm %d", (int)algo);
         return false;
     }
-    if (algo == RP_ALGO_SPLIT_F16 && type != RP_OMEGA_F16) {
-        *st = fail(ctx, RP_ERR_INVALID_ARG, "the split-FP16 projection needs an FP16 Omega");
+    if (algo == RP_ALGO_SPLIT_F16 && type == RP_OMEGA_F32) {
+        *st = fail(ctx, RP_ERR_INVALID_ARG, "the split-FP16 projection needs an FP16 or e4m3 Omega");
         return false;
     }
     return true;
+}
+
+// Scratch bytes fill_packed needs to generate Omega of `type` for `algo`.
+size_t raw_bytes(rp_omega_t type, rp_algo_t algo, int64_t n, int64_t r) {
+    if (type == RP_OMEGA_E4M3) return (size_t)n * r * 6 + (((size_t)r * 4 + 255) & ~size_t(255)) + 256;
+    if (algo == RP_ALGO_F32) return (size_t)n * r * (type == RP_OMEGA_F32 ? 4 : 2);
+    return 0;
 }
 
 // Fill `pk` (fragment order for `algo`) from a caller Omega or from the
@@ -272,6 +299,18 @@ bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
 rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void* omega, int64_t ldo,
                       rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
                       const rpmi::PackedOmega& pk, void* scratch, hipStream_t s) {
+    if (type == RP_OMEGA_E4M3) {
+        if (omega) return fail(ctx, RP_ERR_UNSUPPORTED, "a caller e4m3 Omega is not supported (no column scales)");
+        // FP32 Omega, column maxima, then the exact FP16 values Omega8 / s_j
+        char* b = static_cast<char*>(scratch);
+        float* w32 = reinterpret_cast<float*>(b);
+        uint16_t* f16 = reinterpret_cast<uint16_t*>(b + (size_t)n * r * 4);
+        unsigned int* cmax = reinterpret_cast<unsigned int*>(b + (((size_t)n * r * 6 + 255) & ~size_t(255)));
+        RP_HIP(ctx, rpmi::launch_omega_e4m3(tables(ctx), seed, stream_id, n, r, w32, cmax, nullptr, 0, f16, r, nullptr,
+                                            s));
+        RP_HIP(ctx, rpmi::launch_pack_omega(f16, false, n, r, r, pk, algo == RP_ALGO_F32, s));
+        return RP_OK;
+    }
     if (algo == RP_ALGO_SPLIT_F16) {
         if (omega) RP_HIP(ctx, rpmi::launch_pack_omega(omega, false, n, r, ldo, pk, false, s));
         else RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), seed, stream_id, n, r, pk, s));
@@ -487,8 +526,8 @@ rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const voi
     if (omega && ldo < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldo %lld < r %lld", (long long)ldo, (long long)r);
     RP_HIP(ctx, hipSetDevice(ctx->device));
     void* scratch = nullptr;
-    if (!omega && algo == RP_ALGO_F32) {
-        if ((st = ensure_workspace(ctx, (size_t)n * r * (type == RP_OMEGA_F32 ? 4 : 2))) != RP_OK) return st;
+    if (!omega && raw_bytes(type, algo, n, r) > 0) {
+        if ((st = ensure_workspace(ctx, raw_bytes(type, algo, n, r))) != RP_OK) return st;
         scratch = ctx->ws;
     }
     return fill_packed(ctx, seed, stream_id, omega, ldo, type, n, r, algo, pk, scratch, (hipStream_t)stream);
@@ -539,10 +578,9 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
     if (!proj_layout_ok(ctx, A, &st)) return st;
     rpmi::PackedOmega pk = packed_geometry(n, r, algo, nullptr);
     const size_t pbytes = packed_bytes(pk, algo);
-    const bool need_raw = !omega && algo == RP_ALGO_F32;
     const size_t raw_off = (pbytes + 255) & ~size_t(255);
-    const size_t raw_bytes = need_raw ? (size_t)n * r * (omega_type == RP_OMEGA_F32 ? 4 : 2) : 0;
-    if ((st = ensure_workspace(ctx, raw_off + raw_bytes)) != RP_OK) return st;
+    const size_t rb = omega ? 0 : raw_bytes(omega_type, algo, n, r);
+    if ((st = ensure_workspace(ctx, raw_off + rb)) != RP_OK) return st;
     pk.data = ctx->ws;
     void* raw = static_cast<char*>(ctx->ws) + raw_off;
     if ((st = fill_packed(ctx, seed, stream_id, omega, ldo, omega_type, n, r, algo, pk, raw, s)) != RP_OK)
@@ -711,7 +749,7 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     Arena ar;
     rpmi::PackedOmega pk = packed_geometry(n, p, algo, nullptr);
     const size_t o_pk = ar.take(packed_bytes(pk, algo));
-    const size_t o_raw = ar.take(algo == RP_ALGO_F32 ? (size_t)n * p * 4 : 0);   // raw Omega (FP32 path)
+    const size_t o_raw = ar.take(raw_bytes(omega_type, algo, n, p));   // generator scratch
     const size_t o_y = ar.take((size_t)m * p * 4);
     RsvdScratch w;
     const size_t o_w = w.layout(ar, m, n, k, p);
@@ -730,7 +768,8 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
                              void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
-    if (omega_type != RP_OMEGA_F16) return fail(ctx, RP_ERR_UNSUPPORTED, "grouped projections take an FP16 Omega");
+    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_E4M3)
+        return fail(ctx, RP_ERR_UNSUPPORTED, "grouped projections take an FP16 or e4m3 Omega");
     rp_status st;
     for (int32_t g = 0; g < count; ++g) {
         const rp_project_problem& q = probs[g];
@@ -746,10 +785,14 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
     Arena ar;
     std::vector<size_t> off(count);
     std::vector<rpmi::PackedOmega> pk(count);
+    size_t rawb = 0;
     for (int32_t g = 0; g < count; ++g) {
         pk[g] = packed_geometry(probs[g].A.cols, probs[g].r, RP_ALGO_SPLIT_F16, nullptr);
         off[g] = ar.take(packed_bytes(pk[g], RP_ALGO_SPLIT_F16));
+        const size_t rb = raw_bytes(omega_type, RP_ALGO_SPLIT_F16, probs[g].A.cols, probs[g].r);
+        rawb = rb > rawb ? rb : rawb;
     }
+    const size_t o_raw = ar.take(rawb);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     std::vector<rpmi::ProjArgs> grouped;
     for (int32_t g = 0; g < count; ++g) {
@@ -760,7 +803,9 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
             continue;
         }
         pk[g].data = static_cast<char*>(ctx->ws) + off[g];
-        RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), q.seed, q.stream_id, q.A.cols, q.r, pk[g], s));
+        if ((st = fill_packed(ctx, q.seed, q.stream_id, nullptr, 0, omega_type, q.A.cols, q.r, RP_ALGO_SPLIT_F16, pk[g],
+                              static_cast<char*>(ctx->ws) + o_raw, s)) != RP_OK)
+            return st;
         rpmi::ProjArgs a;
         a.A = q.A.ptr; a.m = q.A.rows; a.n = q.A.cols;
         a.s_row = q.A.s_row; a.k_inner = q.A.k_inner; a.s_k_outer = q.A.s_k_outer;
@@ -785,9 +830,9 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                        uint64_t seed, rp_omega_t omega_type, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
-    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_F32)
+    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_F32 && omega_type != RP_OMEGA_E4M3)
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)omega_type);
-    const rp_algo_t algo = omega_type == RP_OMEGA_F16 ? RP_ALGO_SPLIT_F16 : RP_ALGO_F32;
+    const rp_algo_t algo = omega_type == RP_OMEGA_F32 ? RP_ALGO_F32 : RP_ALGO_SPLIT_F16;
     rp_status st;
     for (int32_t g = 0; g < count; ++g)
         if ((st = rsvd_check(ctx, probs[g], power_iters)) != RP_OK) return st;
@@ -809,7 +854,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         o_pk[g] = ar.take(packed_bytes(pk[g], algo));
         o_y[g] = ar.take((size_t)q.m * p * 4);
         mm = q.m > mm ? q.m : mm; mn = q.n > mn ? q.n : mn; mk = q.k > mk ? q.k : mk; mp = p > mp ? p : mp;
-        if (algo == RP_ALGO_F32) raw = (size_t)q.n * p * 4 > raw ? (size_t)q.n * p * 4 : raw;
+        raw = raw_bytes(omega_type, algo, q.n, p) > raw ? raw_bytes(omega_type, algo, q.n, p) : raw;
     }
     const size_t o_raw = ar.take(raw);
     RsvdScratch w;
@@ -1040,18 +1085,16 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     Arena ar;
     size_t o_pk[rpmi::kMaxGroup], o_w[rpmi::kMaxGroup];
     rpmi::PackedOmega pk[rpmi::kMaxGroup];
-    size_t raw_bytes = 0;
+    size_t rawb = 0;
     for (int i = 0; i < N; ++i) {
         const int64_t cols = total / dims[i];
         pk[i] = packed_geometry(cols, ranks[i], algo, nullptr);
         o_pk[i] = ar.take(packed_bytes(pk[i], algo));
         o_w[i] = ar.take((size_t)dims[i] * ranks[i] * 4);
-        if (algo == RP_ALGO_F32) {
-            const size_t rb = (size_t)cols * ranks[i] * (omega_type == RP_OMEGA_F32 ? 4 : 2);
-            raw_bytes = rb > raw_bytes ? rb : raw_bytes;
-        }
+        const size_t rb = raw_bytes(omega_type, algo, cols, ranks[i]);
+        rawb = rb > rawb ? rb : rawb;
     }
-    const size_t o_raw = ar.take(raw_bytes);
+    const size_t o_raw = ar.take(rawb);
     const size_t o_perm = ar.take((size_t)perm_elems * 4);
     const size_t o_qd = ar.take((size_t)maxd * maxr * 8);
     const size_t o_g = ar.take((size_t)maxr * maxr * 8);

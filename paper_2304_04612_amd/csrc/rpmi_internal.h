@@ -94,6 +94,13 @@ int64_t proj_k_block();               // contraction rows per main-loop step
 hipError_t launch_omega_rowmajor(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
                                  int64_t n, int64_t r, bool f32, void* out, int64_t ldo,
                                  hipStream_t s);
+// e4m3 Omega (Omega8 = sat448(RNE_e4m3(w s_j)), s_j a power of two per
+// column, w the FP32 Omega): w32 (n x r) and cmax (r) are scratch; codes
+// (e4m3fn bytes), f16 (the exact FP16 values Omega8 / s_j) and scale (s_j) are
+// written when not NULL.
+hipError_t launch_omega_e4m3(const OmegaTables& t, uint64_t seed, uint32_t stream_id, int64_t n, int64_t r,
+                             float* w32, unsigned int* cmax, uint8_t* codes, int64_t ldc, uint16_t* f16, int64_t ldf,
+                             float* scale, hipStream_t s);
 hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
 hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,

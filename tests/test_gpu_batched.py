@@ -117,3 +117,33 @@ def test_rsvd_batched_full_size_planted():
     worst = max(float(np.abs(host(sv) - sig).max()) for (_, sv, _), sig in zip(outs, sigs))
     print(f"max |sigma - planted| over 256 problems: {worst:.3e}")
     assert worst <= 1e-5
+
+
+def test_rsvd_batched_e4m3_omega():
+    """The e4m3 Omega variant (power-of-two scale per column): same oracle
+    comparison with the e4m3 values; the planted spectrum is still recovered
+    exactly, and the error of a noisy problem is reported beside FP16's."""
+    batch = _planted_batch(6, 91, 100, 600, 6, 20)
+    announce("rsvd_batched e4m3")
+    mats = [dev(a) for a, _, _, _ in batch]
+    ks = [k for _, k, _, _ in batch]
+    ss = [s for _, _, s, _ in batch]
+    outs = rp().rsvd_batched(mats, ks, ss, 0, 31, "e4m3")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, ((a, k, s, sig), (u, sv, vt)) in enumerate(zip(batch, outs)):
+        _, _, val = omega.omega_e4m3(31, j, a.shape[1], k + s)
+        _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), val, k, 0)
+        assert np.abs(host(sv) - sv_o).max() <= 1e-5 * sv_o[0], j
+        assert np.abs(host(sv) - sig).max() <= 1e-5 * sig[0], j
+    # noisy: rank-k approximation error with e4m3 vs FP16 Omega (both near the optimum)
+    rng = np.random.default_rng(5)
+    sig = 10.0 ** (-3.0 * np.arange(30) / 29)
+    a = synth.np_planted(400, 500, sig, rng, noise_std=1e-4)
+    errs = {}
+    for ot in ("f16", "e4m3"):
+        (u, sv, vt), = rp().rsvd_batched([dev(a)], [20], [10], 0, 2, ot)
+        rec = (host(u).astype(np.float64) * host(sv)) @ host(vt).astype(np.float64)
+        errs[ot] = np.linalg.norm(rec - a) / np.linalg.norm(a)
+    opt = np.sqrt(np.sum(np.linalg.svd(a.astype(np.float64), compute_uv=False)[20:] ** 2)) / np.linalg.norm(a)
+    print(f"rank-20 relative error: f16 {errs['f16']:.4e}  e4m3 {errs['e4m3']:.4e}  optimum {opt:.4e}")
+    assert errs["e4m3"] <= 1.5 * errs["f16"] and errs["f16"] <= 3.0 * opt

@@ -43,3 +43,12 @@ def test_zero_sizes():
     rp().rp_omega_generate(2, 0, 1, 0, "f16", out=out)
     torch.cuda.synchronize()
     assert bool((out == 7).all())
+
+
+@pytest.mark.parametrize("n,r", [(3000, 40), (1, 1), (257, 130), (0, 5)])
+def test_e4m3_codes_and_scales_bit_exact(n, r):
+    announce(f"e4m3 omega n={n} r={r}")
+    codes, scale = rp().rp_omega_generate_e4m3(n, r, seed=21, stream_id=4)
+    c_o, s_o, _ = omega.omega_e4m3(21, 4, n, r)
+    assert np.array_equal(host(scale).astype(np.float64), s_o)
+    assert np.array_equal(host(codes), c_o)

@@ -179,3 +179,18 @@ def test_packed_entry_points_match_rp_project():
         y1 = host(rp().rp_project_packed(a, 90, pk, algo=algo))
         y2 = host(rp().rp_project(a, 90, seed=6, stream_id=2, algo=algo))
         assert np.array_equal(y1, y2), algo
+
+
+@pytest.mark.parametrize("algo", ["split_f16", "f32"])
+def test_e4m3_omega_projection(algo):
+    """Generated e4m3 Omega: the projection uses Omega8 / s_j (exact in FP16),
+    within the elementwise bound of the product with those values."""
+    announce(f"e4m3 projection {algo}")
+    rng = np.random.default_rng(12)
+    m, n, r = 300, 2000, 96
+    a = rng.standard_normal((m, n)).astype(np.float32)
+    _, _, val = omega.omega_e4m3(17, 0, n, r)
+    y = host(rp().rp_project(dev(a), r, seed=17, omega_type="e4m3", algo=algo)).astype(np.float64)
+    ref = a.astype(np.float64) @ val
+    bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, val)
+    assert np.all(np.abs(y - ref) <= bound)

@@ -91,3 +91,43 @@ def test_row_subset_equals_full():
     full = omega.omega_f16_bits(8, 1, 300, 21)
     rows = [0, 5, 299, 17]
     assert np.array_equal(omega.omega_f16_bits(8, 1, 0, 21, rows=rows), full[rows])
+
+
+def test_e4m3_encode_is_nearest_by_brute_force():
+    """RNE to e4m3fn against a brute-force search over every finite code:
+    the nearest value, ties to the even mantissa; beyond 448 saturation."""
+    codes = np.arange(256, dtype=np.uint8)
+    vals = omega.e4m3_decode(codes)
+    finite = np.isfinite(vals) & ~((codes & 0x80).astype(bool) & (vals == 0))   # one zero
+    fv, fc = vals[finite], codes[finite]
+    assert np.sum(finite) == 253 and fv.max() == 448.0
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.standard_normal(3000) * 50, rng.uniform(-2 ** -5, 2 ** -5, 2000),
+                        (fv[:, None] + np.array([0.0])[None, :]).ravel(),
+                        (fv[1:] + fv[:-1]) / 2])                  # every value and every midpoint
+    x = x[np.abs(x) <= 448]
+    got = omega.e4m3_decode(omega.e4m3_encode_rne(x))
+    d = np.abs(fv[None, :] - x[:, None])
+    best = d.min(axis=1)
+    for xi, gi, bi, row in zip(x, got, best, d):
+        cand = fc[np.isclose(row, bi, rtol=0, atol=0)]
+        if cand.size == 1:
+            assert gi == omega.e4m3_decode(cand)[0] or (gi == 0 and xi == 0), xi
+        else:                                                      # a tie: the even mantissa
+            even = cand[(cand & 1) == 0]
+            assert gi == omega.e4m3_decode(even)[0], xi
+    assert omega.e4m3_decode(omega.e4m3_encode_rne(np.array([460.0, -1e4])))[0] == 448.0
+
+
+def test_e4m3_omega_scale_and_exactness():
+    codes, scale, val = omega.omega_e4m3(3, 1, 3000, 40)
+    w32 = omega.omega_f32(3, 1, 3000, 40).astype(np.float64)
+    cmax = np.abs(w32).max(axis=0)
+    # the scale is the largest power of two that keeps the column within 448
+    assert np.all(cmax * scale <= 448.0) and np.all(cmax * scale * 2 > 448.0)
+    assert np.all(np.log2(scale) == np.round(np.log2(scale)))
+    # Omega8 / s_j is exact in FP16 (so the FP16 kernels take it unchanged)
+    assert np.array_equal(val.astype(np.float16).astype(np.float64), val)
+    # relative quantisation error of e4m3 (3 mantissa bits): at most 2^-4 for normals
+    big = np.abs(w32 * scale) >= 2.0 ** -6
+    assert np.all(np.abs(val - w32)[big] <= 2.0 ** -4 * np.abs(w32)[big])
