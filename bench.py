@@ -15,6 +15,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -30,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # WRITE_SIZE) and scaled by the same counters on a copy of known size; valid
 # only while the kernel sources hash to the value recorded with it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_split_f16_16384x16384x256_hbm_traffic.txt")
-KERNEL_SOURCES = ("paper_2304_04612_amd/csrc/project.hip", "paper_2304_04612_amd/csrc/rpmi_internal.h")
+KERNEL_SOURCES = ("paper_2304_04612_amd/csrc/proj_common.h", "paper_2304_04612_amd/csrc/project_wide.hip",
+                  "paper_2304_04612_amd/csrc/rpmi_internal.h")
 
 
 def parse():
@@ -40,6 +42,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--cpu-rows", type=int, default=M)
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-rsvd", action="store_true", help="skip the 32768^2 randomized SVD")
+    p.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched RSVD")
     p.add_argument("--a-cache", default=None,
                    help="file holding A (raw FP32, row-major); written on first use, read afterwards")
     return p.parse_args()
@@ -161,7 +165,7 @@ def main():
                                "Haar U,V), Omega 16384x256 FP16 (Philox4x64 + exact FP16 inverse CDF)",
                    "m": M, "n": N, "r": R, "seed_A": SEED_A, "seed_omega": SEED_OMEGA},
         "roofline": {
-            "kernel": "project_split_f16_dma_kernel",
+            "kernel": "project_split_f16_grouped_kernel (256-column tile)",
             "bound": "hbm",
             "achieved": round(alg_bytes / kern_s / 1e9, 1),
             "peak": HBM_PEAK_GBS,
@@ -187,7 +191,99 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"], errs = cpu_leg(a, y, y32, args.cpu_rows)
         out.update(errs)
+    del a, y, y32, pk16, pk32
+    torch.cuda.empty_cache()
+    if not args.no_rsvd:
+        out["rsvd"] = rsvd_leg(rp, synth, torch, dev)
+    if not args.no_batched:
+        out["batched_rsvd"] = batched_leg(rp, synth, torch, dev)
     print(json.dumps(out), flush=True)
+
+
+def rsvd_leg(rp, synth, torch, dev):
+    """Full randomized SVD: A 32768 x 32768 FP32 = U diag(sigma) V^T + noise,
+    planted rank 512 with sigma_i = 10^(-(i-1)/511), noise N(0, (1e-4)^2);
+    k = 512, oversampling 128 (Omega 32768 x 640 FP16), one power iteration,
+    CholeskyQR2 in FP64.  Wall time of rsvd() (inputs resident), and the
+    singular-value error against the planted values, bounded by Weyl's
+    inequality by ||E||_2 ~ 1e-4 * 2 sqrt(32768) = 0.036."""
+    import numpy as np
+    m = n = 32768
+    k, s, q = 512, 128, 1
+    t = time.time()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(103)
+    sig = torch.tensor(10.0 ** (-np.arange(k) / (k - 1)), device=dev, dtype=torch.float64)
+    u = synth.torch_haar(m, k, gen, dev)
+    v = synth.torch_haar(n, k, gen, dev)
+    a = torch.empty((m, n), dtype=torch.float32, device=dev)
+    for r0 in range(0, m, 4096):                       # formed in FP64 row blocks
+        blk = (u[r0:r0 + 4096] * sig) @ v.T
+        blk += torch.randn(blk.shape, generator=gen, device=dev, dtype=torch.float64) * 1e-4
+        a[r0:r0 + 4096] = blk.float()
+    del u, v, blk
+    torch.cuda.synchronize()
+    log(f"RSVD A generated in {time.time() - t:.1f} s")
+    walls = []
+    for rep in range(2):                               # the first call also sizes the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uu, sv, vt = rp.rsvd(a, k, s, q, 203, "f16", "split_f16")
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    status = rp.rp_get_device_status(clear=True)
+    err = float((sv - sig).abs().max().item())
+    log(f"RSVD 32768^2 k=512: wall {walls}, max |sigma - planted| {err:.3e}")
+    del a, uu, vt
+    torch.cuda.empty_cache()
+    return {"workload": "rsvd A 32768x32768 FP32 planted rank 512 (sigma_i=10^(-(i-1)/511)) + N(0,1e-4) noise; "
+                        "k=512, p=640, Omega FP16, q=1, CholeskyQR2 FP64",
+            "wall_s": round(min(walls), 4), "wall_s_first_call": round(walls[0], 4),
+            "max_abs_sigma_err_vs_planted": err, "weyl_bound": 1e-4 * 2 * math.sqrt(m),
+            "device_status": rp.status_string(status)}
+
+
+def batched_leg(rp, synth, torch, dev):
+    """256 randomized SVDs: m, n log-uniform in [512, 8192], planted rank
+    k in [16, 128] with sigma_i = 10^(-3(i-1)/(k-1)), noiseless, width
+    p = k + max(10, ceil(k/4)), Omega_j FP16 (and e4m3) from stream j.  The
+    first call tunes the grouped projection and captures the graph; the timed
+    calls replay it."""
+    import numpy as np
+    shapes = synth.batched_problem_list(256, 105, 512, 8192, 16, 128)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(105)
+    t = time.time()
+    mats, sigs = [], []
+    for m, n, k, p in shapes:
+        sig = torch.tensor(10.0 ** (-3.0 * np.arange(k) / (k - 1)), device=dev, dtype=torch.float64)
+        u = synth.torch_haar(m, k, gen, dev)
+        v = synth.torch_haar(n, k, gen, dev)
+        mats.append(((u * sig) @ v.T).float().contiguous())
+        sigs.append(sig)
+    torch.cuda.synchronize()
+    log(f"batched A generated in {time.time() - t:.1f} s")
+    ks = [k for _, _, k, _ in shapes]
+    ss = [p - k for _, _, k, p in shapes]
+    res = {"workload": "batched rsvd, 256 problems, m,n log-uniform [512,8192], planted rank 16-128, noiseless",
+           "a_bytes": int(sum(4 * m * n for m, n, _, _ in shapes))}
+    for ot in ("f16", "e4m3"):
+        t0 = time.perf_counter()
+        outs = rp.rsvd_batched(mats, ks, ss, 0, 205, ot)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        walls = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            rp.rsvd_batched(mats, ks, ss, 0, 205, ot, outputs=outs)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        err = max(float((sv - sg).abs().max().item()) for (_, sv, _), sg in zip(outs, sigs))
+        res[ot] = {"wall_s_graph_replay": round(min(walls), 5), "wall_s_first_call": round(first, 4),
+                   "max_abs_sigma_err_vs_planted": err,
+                   "device_status": rp.status_string(rp.rp_get_device_status(clear=True))}
+        log(f"batched {ot}: first {first:.3f} s, replay {min(walls) * 1e3:.2f} ms, sigma err {err:.2e}")
+    return res
 
 
 def cpu_leg(a, y, y32, rows):

@@ -408,7 +408,9 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
         // each step is a scheduling region of its own (the barrier above
         // already orders it); one region per group of D steps makes the
         // interleaving solver's work grow much faster than D
+#ifndef RPMI_NO_STEP_REGION
         __builtin_amdgcn_sched_barrier(0);
+#endif
         issue(IntC<(s + D - 1) % D>{});
         mfma_step(hs[cur], ls[cur], stage_at(slot_c));
         split_step(ring[(s + 1) % D], hs[cur ^ 1], ls[cur ^ 1]);
@@ -509,9 +511,10 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
 // Several independent projections in one launch: block b belongs to the
 // problem g with table[g].start <= b < table[g + 1].start (binary search);
 // inside it, blocks enumerate (kz, bm, bn) with bn fastest.
+// With count == 0 the launch is one problem, passed by value in `one`.
 template <class T, int D, bool TWO_ACC>
 __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kernel(const GroupEntry* __restrict__ table,
-                                                                                 int count) {
+                                                                                 int count, const GroupEntry one) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = count - 1;
 #pragma unroll 1
@@ -520,9 +523,10 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kerne
         if (table[mid].start <= b) lo = mid;
         else hi = mid - 1;
     }
-    const ProjArgs p = table[lo].p;
-    const int64_t local = b - table[lo].start;
-    const int64_t tn = table[lo].tiles_n, tm = table[lo].tiles_m;
+    const GroupEntry& e = count > 0 ? table[lo] : one;
+    const ProjArgs p = e.p;
+    const int64_t local = b - e.start;
+    const int64_t tn = e.tiles_n, tm = e.tiles_m;
     const int64_t per_k = tm * tn;
     const int kz = (int)(local / per_k);
     const int64_t rest = local - kz * per_k;

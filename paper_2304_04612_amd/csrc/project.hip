@@ -298,15 +298,15 @@ int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTi
 int64_t split_group_tile_n(int64_t r) { return r <= 128 ? DmaTile128::BN : DmaTile::BN; }
 
 hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                            hipStream_t s) {
-    return narrow ? launch_split_group_narrow(table, count, blocks, s) : launch_split_group_wide(table, count, blocks, s);
+                                            hipStream_t s, const GroupEntry* one) {
+    return narrow ? launch_split_group_narrow(table, count, blocks, one, s)
+                  : launch_split_group_wide(table, count, blocks, one, s);
 }
 
-// The deep-pipeline kernel reads its problem from a device table; a single
-// projection passes a one-entry table through the launch's own argument
-// block (table_slot: device memory for one entry, owned by the caller).
+// The deep-pipeline kernel exists in grouped form only; a single projection
+// is a group of one passed by value.
 template <class C, class TS>
-hipError_t launch_split_with(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s) {
+hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
     using TD = typename C::Tile;
     if (vector_ok(a)) {
         GroupEntry e;
@@ -314,19 +314,16 @@ hipError_t launch_split_with(const ProjArgs& a, GroupEntry* table_slot, hipStrea
         e.tiles_m = (a.m + TD::BM - 1) / TD::BM;
         e.tiles_n = (a.r + TD::BN - 1) / TD::BN;
         e.start = 0;
-        const hipError_t err = hipMemcpyAsync(table_slot, &e, sizeof e, hipMemcpyHostToDevice, s);
-        if (err != hipSuccess) return err;
-        return launch_project_split_f16_grouped(table_slot, 1, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
-                                                TD::BN == 128, s);
+        return launch_project_split_f16_grouped(nullptr, 0, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
+                                                TD::BN == 128, s, &e);
     }
     dim3 grid((unsigned)((a.m + TS::BM - 1) / TS::BM), (unsigned)((a.r + TS::BN - 1) / TS::BN));
     hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, false>), grid, dim3(TS::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_project_split_f16(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s) {
-    return a.r <= 128 ? launch_split_with<NarrowCfg, SplitTile128>(a, table_slot, s)
-                      : launch_split_with<WideCfg, SplitTile>(a, table_slot, s);
+hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
+    return a.r <= 128 ? launch_split_with<NarrowCfg, SplitTile128>(a, s) : launch_split_with<WideCfg, SplitTile>(a, s);
 }
 
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {

@@ -5,11 +5,13 @@
 
 namespace rpmi {
 
-hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, hipStream_t s) {
-    if (blocks <= 0 || count <= 0) return hipSuccess;
+hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
+                                  hipStream_t s) {
+    if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
     using T = NarrowCfg::Tile;
+    const GroupEntry single = one ? *one : GroupEntry{};
     hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, NarrowCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
-                       dim3(T::THREADS), 0, s, table, count);
+                       dim3(T::THREADS), 0, s, table, one ? 0 : count, single);
     return hipGetLastError();
 }
 

@@ -379,7 +379,7 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
             a.counters = ctx->split_counters;
             a.partial = static_cast<float*>(ctx->split_ws);
         }
-        RP_HIP(ctx, rpmi::launch_project_split_f16(a, ctx->table, s));
+        RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
     } else {
         RP_HIP(ctx, rpmi::launch_project_f32(a, s));
     }
@@ -989,7 +989,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                 a.Y = reinterpret_cast<float*>(base + o_y[g]); a.ldy = p; a.r = p;
                 a.status = ctx->d_status;
                 a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
-                RP_HIP(ctx, rpmi::launch_project_split_f16(a, nullptr, cs));
+                RP_HIP(ctx, rpmi::launch_project_split_f16(a, cs));
             } else if ((r2 = launch_projection(ctx, &dA, p, pk[g], algo, reinterpret_cast<float*>(base + o_y[g]), p,
                                                cs)) != RP_OK) {
                 return r2;

@@ -66,10 +66,13 @@ struct GroupEntry {
 };
 int64_t split_group_tile_m(int64_t r);
 int64_t split_group_tile_n(int64_t r);
+// `one` != NULL: a single problem passed by value (table and count unused)
 hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                            hipStream_t s);
-hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, hipStream_t s);
-hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, hipStream_t s);
+                                            hipStream_t s, const GroupEntry* one = nullptr);
+hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
+                                   hipStream_t s);
+hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
+                                     hipStream_t s);
 bool split_vector_ok(const ProjArgs& a);
 
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
@@ -105,7 +108,7 @@ hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
 hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
                              const PackedOmega& dst, bool dst_f32, hipStream_t s);
-hipError_t launch_project_split_f16(const ProjArgs& a, GroupEntry* table_slot, hipStream_t s);
+hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s);
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s);
 hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                              hipStream_t s);
