@@ -165,7 +165,7 @@ def main():
                                "Haar U,V), Omega 16384x256 FP16 (Philox4x64 + exact FP16 inverse CDF)",
                    "m": M, "n": N, "r": R, "seed_A": SEED_A, "seed_omega": SEED_OMEGA},
         "roofline": {
-            "kernel": "project_split_f16_grouped_kernel (256-column tile)",
+            "kernel": "project_split_f16_single_kernel (256-column tile)",
             "bound": "hbm",
             "achieved": round(alg_bytes / kern_s / 1e9, 1),
             "peak": HBM_PEAK_GBS,

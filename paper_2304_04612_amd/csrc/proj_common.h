@@ -405,12 +405,14 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
         constexpr int s = decltype(slot_c)::value;
         constexpr int cur = s & 1;
         wait_vm_barrier<(D - 3) * OPS>();
-        // each step is a scheduling region of its own (the barrier above
-        // already orders it); one region per group of D steps makes the
-        // interleaving solver's work grow much faster than D
-#ifndef RPMI_NO_STEP_REGION
-        __builtin_amdgcn_sched_barrier(0);
+        // a scheduling region every RPMI_STEP_REGION steps (the barrier above
+        // already orders the steps): larger regions schedule better, but the
+        // interleaving solver's time grows steeply with the region (one region
+        // per group of 6 steps takes minutes per instantiation)
+#ifndef RPMI_STEP_REGION
+#define RPMI_STEP_REGION 3
 #endif
+        if constexpr (RPMI_STEP_REGION > 0 && s % RPMI_STEP_REGION == 0) __builtin_amdgcn_sched_barrier(0);
         issue(IntC<(s + D - 1) % D>{});
         mfma_step(hs[cur], ls[cur], stage_at(slot_c));
         split_step(ring[(s + 1) % D], hs[cur ^ 1], ls[cur ^ 1]);
@@ -511,10 +513,13 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
 // Several independent projections in one launch: block b belongs to the
 // problem g with table[g].start <= b < table[g + 1].start (binary search);
 // inside it, blocks enumerate (kz, bm, bn) with bn fastest.
-// With count == 0 the launch is one problem, passed by value in `one`.
+// Several independent projections in one launch: block b belongs to the
+// problem g with table[g].start <= b < table[g + 1].start (binary search on
+// a block-uniform index, so the entry is read with scalar loads); inside it,
+// blocks enumerate (kz, bm, bn) with bn fastest.
 template <class T, int D, bool TWO_ACC>
 __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kernel(const GroupEntry* __restrict__ table,
-                                                                                 int count, const GroupEntry one) {
+                                                                                 int count) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = count - 1;
 #pragma unroll 1
@@ -523,13 +528,22 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_grouped_kerne
         if (table[mid].start <= b) lo = mid;
         else hi = mid - 1;
     }
-    const GroupEntry& e = count > 0 ? table[lo] : one;
-    const ProjArgs p = e.p;
+    const GroupEntry& e = table[lo];
     const int64_t local = b - e.start;
     const int64_t tn = e.tiles_n, tm = e.tiles_m;
     const int64_t per_k = tm * tn;
     const int kz = (int)(local / per_k);
     const int64_t rest = local - kz * per_k;
+    split_dma_body<T, D, TWO_ACC>(e.p, rest / tn, rest % tn, kz, tn);
+}
+
+// One projection, its arguments by value (kernel argument segment).
+template <class T, int D, bool TWO_ACC>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_single_kernel(ProjArgs p) {
+    const int64_t tn = (p.r + T::BN - 1) / T::BN, tm = (p.m + T::BM - 1) / T::BM;
+    const int64_t b = blockIdx.x, per_k = tm * tn;
+    const int kz = (int)(b / per_k);
+    const int64_t rest = b - kz * per_k;
     split_dma_body<T, D, TWO_ACC>(p, rest / tn, rest % tn, kz, tn);
 }
 

@@ -9,9 +9,12 @@ hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t b
                                   hipStream_t s) {
     if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
     using T = WideCfg::Tile;
-    const GroupEntry single = one ? *one : GroupEntry{};
-    hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, WideCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
-                       dim3(T::THREADS), 0, s, table, one ? 0 : count, single);
+    if (one)
+        hipLaunchKernelGGL((project_split_f16_single_kernel<T, WideCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
+                           dim3(T::THREADS), 0, s, one->p);
+    else
+        hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, WideCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
+                           dim3(T::THREADS), 0, s, table, count);
     return hipGetLastError();
 }
 
