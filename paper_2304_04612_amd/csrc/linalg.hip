@@ -277,6 +277,115 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(double* W, double* V, 
     if (!converged && tid == 0) atomicOr(status, kStatusNotConverged);
 }
 
+// ---------------------------------------------------------------- parallel one-sided Jacobi
+// Many workgroups per round: one workgroup per column pair, one launch per
+// round of the round-robin (circle) ordering, so that a sweep streams the
+// columns at full-chip bandwidth instead of through one compute unit.  W and
+// V are held column-major during the iteration (column j contiguous).  Per
+// problem, flags[0] = converged, flags[1 + (sweep & 1)] = a rotation happened
+// in that sweep, flags[3] = sweeps done.  Every kernel of a converged problem
+// returns at once.
+__global__ void jacobi_prep_kernel(const JacobiProb* tab) {
+    const JacobiProb P = tab[blockIdx.y];
+    const int n = P.n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / n), j = (int)(e % n);
+        if (r < j) {                                  // transpose W in place: row-major -> column-major
+            const double t = P.W[(int64_t)r * n + j];
+            P.W[(int64_t)r * n + j] = P.W[(int64_t)j * n + r];
+            P.W[(int64_t)j * n + r] = t;
+        }
+        P.V[e] = r == j ? 1.0 : 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) P.flags[threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab, int count, int round, int sweep,
+                                                           double tol) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].pair_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const JacobiProb P = tab[lo];
+    const int n = P.n, m = n + (n & 1);
+    if (round >= m - 1 || P.flags[0]) return;
+    const int k = b - P.pair_start;                   // pair k: positions k and m - 1 - k
+    // circle method: position 0 holds player 0, position i >= 1 holds
+    // 1 + ((i - 1 + round) mod (m - 1))
+    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
+    int a = player(k), c = player(m - 1 - k);
+    if (a > c) { const int t = a; a = c; c = t; }
+    if (c >= n) return;                               // the dummy of an odd n
+    double* wa = P.W + (int64_t)a * n;
+    double* wc = P.W + (int64_t)c * n;
+    __shared__ double red[3][4];
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double x = wa[r], y = wc[r];
+        al += x * x; be += y * y; ga += x * y;
+    }
+    al = block_sum256(al, red[0]);
+    be = block_sum256(be, red[1]);
+    ga = block_sum256(ga, red[2]);
+    if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) return;
+    // the rotation that zeroes the off-diagonal of the pair's 2x2 Gram
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    double* va = P.V + (int64_t)a * n;
+    double* vc = P.V + (int64_t)c * n;
+    for (int r = threadIdx.x; r < n; r += 256) {
+        const double x = wa[r], y = wc[r];
+        wa[r] = cs * x - sn * y;
+        wc[r] = sn * x + cs * y;
+        const double vx = va[r], vy = vc[r];
+        va[r] = cs * vx - sn * vy;
+        vc[r] = sn * vx + cs * vy;
+    }
+    if (threadIdx.x == 0) P.flags[1 + (sweep & 1)] = 1;
+}
+
+__global__ void jacobi_sweep_end_kernel(const JacobiProb* tab, int count, int sweep) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) {
+        int* f = tab[g].flags;
+        if (f[0]) continue;
+        if (f[1 + (sweep & 1)] == 0) f[0] = 1;
+        f[1 + ((sweep + 1) & 1)] = 0;
+        f[3] = sweep + 1;
+    }
+}
+
+__global__ void jacobi_final_kernel(const JacobiProb* tab, unsigned int* status) {
+    const JacobiProb P = tab[blockIdx.y];
+    const int n = P.n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / n), j = (int)(e % n);
+        if (r < j) {                                  // back to row-major
+            double t = P.W[(int64_t)r * n + j];
+            P.W[(int64_t)r * n + j] = P.W[(int64_t)j * n + r];
+            P.W[(int64_t)j * n + r] = t;
+            t = P.V[(int64_t)r * n + j];
+            P.V[(int64_t)r * n + j] = P.V[(int64_t)j * n + r];
+            P.V[(int64_t)j * n + r] = t;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !P.flags[0]) atomicOr(status, kStatusNotConverged);
+}
+
 // sigma_j = |w_j|; rank the columns by sigma descending (ties by index); write
 // sigma in that order and the permutation (one workgroup, n <= 1024).
 __global__ __launch_bounds__(1024) void svd_finish_kernel(const double* W, int n, double* sig_sorted,
@@ -431,6 +540,28 @@ hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, u
                       hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, W, V, n, max_sweeps, tol, status);
+    return hipGetLastError();
+}
+
+hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
+                            double tol, unsigned int* status, hipStream_t s) {
+    if (count <= 0 || max_n <= 0) return hipSuccess;
+    hipError_t e;
+    const int gx = grid1d((int64_t)max_n * max_n) < 1024 ? grid1d((int64_t)max_n * max_n) : 1024;
+    hipLaunchKernelGGL(jacobi_prep_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int max_m = max_n + (max_n & 1);
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        for (int round = 0; round < max_m - 1; ++round) {
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)total_pairs), dim3(256), 0, s, tab, count, round,
+                               sweep, tol);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, tab,
+                           count, sweep);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(jacobi_final_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab, status);
     return hipGetLastError();
 }
 

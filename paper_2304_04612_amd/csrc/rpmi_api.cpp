@@ -39,6 +39,8 @@ struct rp_ctx_s {
     uint64_t graph_key = 0;
     rpmi::GroupEntry* graph_table = nullptr;
     size_t graph_table_entries = 0;
+    rpmi::JacobiProb* graph_jtab = nullptr;   // the batched Jacobi table read by the graph
+    size_t graph_jtab_entries = 0;
     std::unordered_map<uint64_t, double> tuned_scale;
 };
 
@@ -186,6 +188,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->table) (void)hipFree(ctx->table);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
+    if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RP_OK;
@@ -630,10 +633,12 @@ rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy,
 // fragment order for the power scheme's projections.
 struct RsvdScratch {
     int64_t m = 0, n = 0, k = 0, p = 0;
-    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, bytes;
+    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_jt, o_jf, bytes;
     float *Q, *Z, *W;
     double *Qd, *G, *X, *L1, *MW, *MV, *sig, *Ur, *Vr;
     int* ord;
+    int* jflags;                       // Jacobi flags (4 ints)
+    rpmi::JacobiProb* jtab;            // a one-entry Jacobi table (device)
     rpmi::PackedOmega pkw;
 
     // reserve the scratch in `ar` (one block); returns its offset
@@ -656,6 +661,8 @@ struct RsvdScratch {
         o_vr = ar.take((size_t)p * k * 8);
         pkw = packed_geometry(n, p, RP_ALGO_F32, nullptr);
         o_pkw = ar.take(packed_bytes(pkw, RP_ALGO_F32));
+        o_jt = ar.take(sizeof(rpmi::JacobiProb));
+        o_jf = ar.take(4 * sizeof(int));
         bytes = ar.used;
         return outer.take(bytes);
     }
@@ -674,8 +681,13 @@ struct RsvdScratch {
         Ur = reinterpret_cast<double*>(b + o_ur);
         Vr = reinterpret_cast<double*>(b + o_vr);
         pkw.data = b + o_pkw;
+        jtab = reinterpret_cast<rpmi::JacobiProb*>(b + o_jt);
+        jflags = reinterpret_cast<int*>(b + o_jf);
     }
 };
+
+constexpr int kJacobiSweeps = 16;
+constexpr double kJacobiTol = 1e-14;
 
 rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) {
     const int64_t p = q.k + q.oversample;
@@ -692,13 +704,14 @@ rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) 
     return RP_OK;
 }
 
-// Algorithm 1 after Y = A Omega: the power scheme (re-orthonormalised), then
-// Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B, SVD of R_B^T, U and V^T.  Launches
-// kernels and device-to-device copies only (capturable in a graph).
-rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
-                                int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
+// Algorithm 1 after Y = A Omega, up to the small SVD: the power scheme
+// (re-orthonormalised), then Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B with R_B^T
+// left in w.MW.  Launches kernels and device-to-device copies only
+// (capturable in a graph).
+rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p, int32_t power_iters,
+                          float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
-    const int64_t m = q.m, n = q.n, k = q.k, lda = q.lda;
+    const int64_t m = q.m, n = q.n, lda = q.lda;
     const float* A = q.A;
     for (int32_t t = 0; t < power_iters; ++t) {
         if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
@@ -714,15 +727,31 @@ rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_pro
     // line 3: B^T = A^T Q (n x p)
     RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
     // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
-    if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
-    // SVD of R_B^T = U_r S V_r^T: then B = U_r S (Q_B V_r)^T
-    RP_HIP(ctx, rpmi::jacobi_svd(w.MW, w.MV, (int)p, 40, 1e-14, ctx->d_status, s));
+    return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, s);
+}
+
+// After the Jacobi SVD of R_B^T = U_r S V_r^T (so B = U_r S (Q_B V_r)^T):
+// S, U = Q U_r[:, :k] and V^T = (Q_B V_r[:, :k])^T.
+rp_status rsvd_after_svd(rp_ctx ctx, const rp_rsvd_problem& q, int64_t p, const RsvdScratch& w, hipStream_t s) {
+    const int64_t m = q.m, n = q.n, k = q.k;
     RP_HIP(ctx, rpmi::svd_finish(w.MW, w.MV, (int)p, (int)k, w.sig, w.ord, w.Ur, w.Vr, s));
     RP_HIP(ctx, hipMemcpyAsync(q.S, w.sig, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
-    // line 5: U = Q U_r[:, :k] (m x k); V^T = (Q_B V_r[:, :k])^T (k x n)
     RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, w.Q, p, 1, w.Ur, k, 1, 0.0, q.U, q.ldu, 1, s)));
     RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, w.W, p, 1, w.Vr, k, 1, 0.0, q.VT, 1, q.ldvt, s)));
     return RP_OK;
+}
+
+// The whole of Algorithm 1 after the projection, for one problem (the
+// Jacobi table entry is written with a stream-ordered host copy).
+rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
+                                int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
+    rp_status st;
+    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s)) != RP_OK) return st;
+    const rpmi::JacobiProb jp{w.MW, w.MV, (int)p, 0, w.jflags};
+    RP_HIP(ctx, hipMemcpyAsync(w.jtab, &jp, sizeof jp, hipMemcpyHostToDevice, s));
+    RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,
+                                       ctx->d_status, s));
+    return rsvd_after_svd(ctx, q, p, w, s);
 }
 
 uint64_t mix(uint64_t h, uint64_t v) {
@@ -857,12 +886,17 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         raw = raw_bytes(omega_type, algo, q.n, p) > raw ? raw_bytes(omega_type, algo, q.n, p) : raw;
     }
     const size_t o_raw = ar.take(raw);
-    RsvdScratch w;
-    const size_t o_w = w.layout(ar, mm, mn, mk, mp);
+    // per problem its own scratch (the stages before and after the grouped
+    // Jacobi SVD keep Q, Q_B and R_B^T of every problem)
+    std::vector<RsvdScratch> ws(count);
+    std::vector<size_t> o_ws(count);
+    for (int32_t g = 0; g < count; ++g)
+        o_ws[g] = ws[g].layout(ar, probs[g].m, probs[g].n, probs[g].k, probs[g].k + probs[g].oversample);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     char* base = static_cast<char*>(ctx->ws);
     for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
-    w.bind(base + o_w);
+    for (int32_t g = 0; g < count; ++g) ws[g].bind(base + o_ws[g]);
+    (void)mm; (void)mn; (void)mk;
 
     // projections of the 16-byte-path problems go out grouped
     std::vector<rpmi::ProjArgs> grouped;
@@ -956,6 +990,22 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         RP_HIP(ctx, hipMemcpy(ctx->graph_table, gp.entries.data(), gp.entries.size() * sizeof(rpmi::GroupEntry),
                               hipMemcpyHostToDevice));
     }
+    std::vector<rpmi::JacobiProb> jt(count);
+    int jpairs = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const int p = (int)(probs[g].k + probs[g].oversample);
+        jt[g] = rpmi::JacobiProb{ws[g].MW, ws[g].MV, p, jpairs, ws[g].jflags};
+        jpairs += (p + 1) / 2;
+    }
+    if ((size_t)count > ctx->graph_jtab_entries) {
+        if (ctx->graph_jtab) RP_HIP(ctx, hipFree(ctx->graph_jtab));
+        ctx->graph_jtab = nullptr;
+        ctx->graph_jtab_entries = 0;
+        RP_HIP(ctx, hipMalloc(&ctx->graph_jtab, (size_t)count * sizeof(rpmi::JacobiProb)));
+        ctx->graph_jtab_entries = count;
+    }
+    rpmi::JacobiProb* jtab = ctx->graph_jtab;
+    RP_HIP(ctx, hipMemcpy(jtab, jt.data(), jt.size() * sizeof(rpmi::JacobiProb), hipMemcpyHostToDevice));
     RP_HIP(ctx, hipDeviceSynchronize());
 
     // capture: Omega generation, the grouped projections, then every
@@ -998,13 +1048,14 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         for (int32_t g = 0; g < count; ++g) {
             const rp_rsvd_problem& q = probs[g];
             const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
-            RsvdScratch wg = w;
-            wg.m = q.m; wg.n = q.n; wg.k = q.k; wg.p = q.k + q.oversample;
-            wg.pkw = packed_geometry(q.n, wg.p, RP_ALGO_F32, w.pkw.data);
-            r2 = rsvd_after_projection(ctx, dA, q, q.k + q.oversample, power_iters,
-                                       reinterpret_cast<float*>(base + o_y[g]), wg, cs);
+            r2 = rsvd_before_svd(ctx, dA, q, q.k + q.oversample, power_iters, reinterpret_cast<float*>(base + o_y[g]),
+                                 ws[g], cs);
             if (r2 != RP_OK) return r2;
         }
+        // one parallel Jacobi SVD over every problem's R_B^T
+        RP_HIP(ctx, rpmi::jacobi_svd_group(jtab, count, jpairs, (int)mp, kJacobiSweeps, kJacobiTol, ctx->d_status, cs));
+        for (int32_t g = 0; g < count; ++g)
+            if ((r2 = rsvd_after_svd(ctx, probs[g], probs[g].k + probs[g].oversample, ws[g], cs)) != RP_OK) return r2;
         return RP_OK;
     };
     const rp_status body_st = body();

@@ -132,6 +132,18 @@ hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int
 hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s);
 hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, unsigned int* status,
                       hipStream_t s);
+// One square problem of the parallel one-sided Jacobi SVD: W (n x n,
+// row-major in and out) becomes W V with orthogonal columns; pair_start = sum
+// of ceil(n/2) over the problems before it; flags: 4 ints of device scratch.
+struct JacobiProb {
+    double* W;
+    double* V;
+    int n;
+    int pair_start;
+    int* flags;
+};
+hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
+                            double tol, unsigned int* status, hipStream_t s);
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
 hipError_t convert_f64_f32(const double* x, float* y, int64_t count, hipStream_t s);
