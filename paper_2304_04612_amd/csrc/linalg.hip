@@ -277,6 +277,15 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(double* W, double* V, 
     if (!converged && tid == 0) atomicOr(status, kStatusNotConverged);
 }
 
+// G = sum over z of the split partials, in the fixed order z = 0, 1, ...
+__global__ void sum_partials_kernel(const double* __restrict__ part, int64_t count, int nsplit, double* __restrict__ G) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = part[e];
+        for (int z = 1; z < nsplit; ++z) acc += part[(int64_t)z * count + e];
+        G[e] = acc;
+    }
+}
+
 // ---------------------------------------------------------------- parallel one-sided Jacobi
 // Many workgroups per round: one workgroup per column pair, one launch per
 // round of the round-robin (circle) ordering, so that a sweep streams the
@@ -474,6 +483,14 @@ template hipError_t gemm_acc64<float, double, double>(int64_t, int64_t, int64_t,
 template hipError_t gemm_acc64<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
                                                     int64_t, const float*, int64_t, int64_t, double, float*,
                                                     int64_t, int64_t, hipStream_t);
+template hipError_t gemm_acc64_batched<float, float, double>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                             int64_t, int64_t, const float*, int64_t, int64_t, int64_t,
+                                                             double, double*, int64_t, int64_t, int64_t, int64_t,
+                                                             hipStream_t);
+template hipError_t gemm_acc64_batched<double, double, double>(int64_t, int64_t, int64_t, double, const double*,
+                                                               int64_t, int64_t, int64_t, const double*, int64_t,
+                                                               int64_t, int64_t, double, double*, int64_t, int64_t,
+                                                               int64_t, int64_t, hipStream_t);
 template hipError_t gemm_acc64_batched<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
                                                             int64_t, int64_t, const float*, int64_t, int64_t, int64_t,
                                                             double, float*, int64_t, int64_t, int64_t, int64_t,
@@ -542,6 +559,32 @@ hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, u
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, W, V, n, max_sweeps, tol, status);
     return hipGetLastError();
 }
+
+template <class T>
+hipError_t gram_acc64(int64_t p, int64_t K, const T* Y, int64_t ldy, double* G, double* partial, int max_split,
+                      hipStream_t s) {
+    if (p <= 0) return hipSuccess;
+    const int64_t tiles = ((p + GT - 1) / GT) * ((p + GT - 1) / GT);
+    int64_t S = 512 / tiles;                         // enough workgroups for the chip
+    S = S > max_split ? max_split : S;
+    S = S > K / 512 ? K / 512 : S;                   // at least 512 contraction rows per part
+    if (S <= 1 || !partial)
+        return gemm_acc64<T, T, double>(p, p, K, 1.0, Y, 1, ldy, Y, ldy, 1, 0.0, G, p, 1, s);
+    const int64_t Kc = ((K + S - 1) / S + GK - 1) / GK * GK;
+    const int64_t parts = (K + Kc - 1) / Kc;         // the first parts - 1 are full
+    const int64_t last = K - (parts - 1) * Kc;
+    hipError_t e = gemm_acc64_batched<T, T, double>(p, p, Kc, 1.0, Y, 1, ldy, Kc * ldy, Y, ldy, 1, Kc * ldy, 0.0,
+                                                    partial, p, 1, p * p, parts - 1, s);
+    if (e != hipSuccess) return e;
+    e = gemm_acc64<T, T, double>(p, p, last, 1.0, Y + (parts - 1) * Kc * ldy, 1, ldy, Y + (parts - 1) * Kc * ldy, ldy,
+                                 1, 0.0, partial + (parts - 1) * p * p, p, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(grid1d(p * p)), dim3(256), 0, s, partial, p * p, (int)parts, G);
+    return hipGetLastError();
+}
+
+template hipError_t gram_acc64<float>(int64_t, int64_t, const float*, int64_t, double*, double*, int, hipStream_t);
+template hipError_t gram_acc64<double>(int64_t, int64_t, const double*, int64_t, double*, double*, int, hipStream_t);
 
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
                             double tol, unsigned int* status, hipStream_t s) {

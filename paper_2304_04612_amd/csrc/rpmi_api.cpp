@@ -609,18 +609,19 @@ struct Arena {
 // Q (FP32, ldq) with orthonormal columns spanning Y, and, if M != NULL, the
 // p x p lower-triangular product L1 L2 of the two Cholesky factors
 // (= R^T for R = R2 R1, Y = Q R).  Scratch: Qd (m x p FP64), G, X (p x p FP64
-// each) and L1 (p x p FP64, kept only when M is requested).
+// each), L1 (p x p FP64, kept only when M is requested) and GP (split Gram
+// partials, kGramSplit p x p FP64).
 rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy, float* Q, int64_t ldq,
-                  double* M, double* Qd, double* G, double* X, double* L1, hipStream_t s) {
+                  double* M, double* Qd, double* G, double* X, double* L1, double* GP, hipStream_t s) {
     unsigned int* st = ctx->d_status;
     // pass 1: G = Y^T Y, G = L L^T, X = L^-1, Qd = Y X^T  (= Y R^-1)
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, double>(p, p, m, 1.0, Y, 1, ldy, Y, ldy, 1, 0.0, G, p, 1, s)));
+    RP_HIP(ctx, rpmi::gram_acc64<float>(p, m, Y, ldy, G, GP, rpmi::kGramSplit, s));
     RP_HIP(ctx, rpmi::potrf_lower(G, p, p, st, s));
     RP_HIP(ctx, rpmi::trtri_lower(G, p, X, p, p, s));
     RP_HIP(ctx, (rpmi::gemm_acc64<float, double, double>(m, p, p, 1.0, Y, ldy, 1, X, 1, p, 0.0, Qd, p, 1, s)));
     if (M) RP_HIP(ctx, hipMemcpyAsync(L1, G, (size_t)p * p * sizeof(double), hipMemcpyDeviceToDevice, s));
     // pass 2 on Qd
-    RP_HIP(ctx, (rpmi::gemm_acc64<double, double, double>(p, p, m, 1.0, Qd, 1, p, Qd, p, 1, 0.0, G, p, 1, s)));
+    RP_HIP(ctx, rpmi::gram_acc64<double>(p, m, Qd, p, G, GP, rpmi::kGramSplit, s));
     RP_HIP(ctx, rpmi::potrf_lower(G, p, p, st, s));
     RP_HIP(ctx, rpmi::trtri_lower(G, p, X, p, p, s));
     RP_HIP(ctx, (rpmi::gemm_acc64<double, double, float>(m, p, p, 1.0, Qd, p, 1, X, 1, p, 0.0, Q, ldq, 1, s)));
@@ -633,9 +634,9 @@ rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy,
 // fragment order for the power scheme's projections.
 struct RsvdScratch {
     int64_t m = 0, n = 0, k = 0, p = 0;
-    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_jt, o_jf, bytes;
+    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_gp, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_jt, o_jf, bytes;
     float *Q, *Z, *W;
-    double *Qd, *G, *X, *L1, *MW, *MV, *sig, *Ur, *Vr;
+    double *Qd, *G, *X, *L1, *GP, *MW, *MV, *sig, *Ur, *Vr;
     int* ord;
     int* jflags;                       // Jacobi flags (4 ints)
     rpmi::JacobiProb* jtab;            // a one-entry Jacobi table (device)
@@ -653,6 +654,7 @@ struct RsvdScratch {
         o_g = ar.take((size_t)p * p * 8);
         o_x = ar.take((size_t)p * p * 8);
         o_l1 = ar.take((size_t)p * p * 8);
+        o_gp = ar.take((size_t)rpmi::kGramSplit * p * p * 8);
         o_mw = ar.take((size_t)p * p * 8);
         o_mv = ar.take((size_t)p * p * 8);
         o_sig = ar.take((size_t)p * 8);
@@ -674,6 +676,7 @@ struct RsvdScratch {
         G = reinterpret_cast<double*>(b + o_g);
         X = reinterpret_cast<double*>(b + o_x);
         L1 = reinterpret_cast<double*>(b + o_l1);
+        GP = reinterpret_cast<double*>(b + o_gp);
         MW = reinterpret_cast<double*>(b + o_mw);
         MV = reinterpret_cast<double*>(b + o_mv);
         sig = reinterpret_cast<double*>(b + o_sig);
@@ -714,20 +717,20 @@ rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& 
     const int64_t m = q.m, n = q.n, lda = q.lda;
     const float* A = q.A;
     for (int32_t t = 0; t < power_iters; ++t) {
-        if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+        if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Z = A^T Q (n x p)
         RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
-        if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+        if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Y = A W (FP32 x FP32): the FP32 projection kernel with W in fragment order
         RP_HIP(ctx, rpmi::launch_pack_omega(w.W, true, n, p, p, w.pkw, true, s));
         if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
     }
     // Algorithm 1 line 2: Q = QR(Y)
-    if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, s)) != RP_OK) return st;
+    if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
     // line 3: B^T = A^T Q (n x p)
     RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
     // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
-    return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, s);
+    return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, w.GP, s);
 }
 
 // After the Jacobi SVD of R_B^T = U_r S V_r^T (so B = U_r S (Q_B V_r)^T):
@@ -1151,6 +1154,7 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     const size_t o_g = ar.take((size_t)maxr * maxr * 8);
     const size_t o_x = ar.take((size_t)maxr * maxr * 8);
     const size_t o_l1 = ar.take((size_t)maxr * maxr * 8);
+    const size_t o_gp = ar.take((size_t)rpmi::kGramSplit * maxr * maxr * 8);
     const size_t o_t0 = ar.take((size_t)tmax * 4);
     const size_t o_t1 = ar.take((size_t)tmax * 4);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
@@ -1207,8 +1211,9 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     double* G = reinterpret_cast<double*>(base + o_g);
     double* Xs = reinterpret_cast<double*>(base + o_x);
     double* L1 = reinterpret_cast<double*>(base + o_l1);
+    double* GP = reinterpret_cast<double*>(base + o_gp);
     for (int i = 0; i < N; ++i)
-        if ((st = cholqr2(ctx, dims[i], ranks[i], W[i], ldw[i], factors[i], ranks[i], nullptr, Qd, G, Xs, L1, s)) !=
+        if ((st = cholqr2(ctx, dims[i], ranks[i], W[i], ldw[i], factors[i], ranks[i], nullptr, Qd, G, Xs, L1, GP, s)) !=
             RP_OK)
             return st;
     // core g = X x_1 Q_1^T ... x_N Q_N^T, one mode at a time: T has shape

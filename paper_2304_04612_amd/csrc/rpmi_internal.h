@@ -124,6 +124,13 @@ template <class TA, class TB, class TC>
 hipError_t gemm_acc64_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
                               int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
                               int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s);
+// G = Y^T Y (p x p, row-major) for Y (K x p, leading dimension ldy), FP64
+// accumulation; long contractions are split into up to max_split parts
+// (partial: max_split * p * p doubles) summed in a fixed order.
+constexpr int kGramSplit = 32;
+template <class T>
+hipError_t gram_acc64(int64_t p, int64_t K, const T* Y, int64_t ldy, double* G, double* partial, int max_split,
+                      hipStream_t s);
 // dst[i][b][p] = src[b][i][p], src of shape [B, I, P] in C order
 hipError_t launch_swap01(const float* src, int64_t B, int64_t I, int64_t P, float* dst, hipStream_t s);
 hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, hipStream_t s);
