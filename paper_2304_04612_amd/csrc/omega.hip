@@ -103,43 +103,40 @@ __host__ __device__ __forceinline__ int frag_slot(int g, int e) {
 // One thread: fragment (kb, nt), lane group g, four adjacent columns c4.
 // Eight Philox blocks (the eight rows of the group's slots) give 32 values,
 // stored as the 16-byte fragments of lanes 16 g + 4 c4 + w, w = 0..3.
-__global__ void omega_packed_f16_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
-                                        int64_t n, int64_t r, uint16_t* dst,
-                                        int64_t kb_count, int64_t nt_count) {
-    const int64_t total = kb_count * nt_count * 16;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int c4 = (int)(q & 3), g = (int)((q >> 2) & 3);
-        const int64_t frag = q >> 4;                  // kb * nt_count + nt
-        const int64_t kb = frag / nt_count, nt = frag - kb * nt_count;
-        uint16_t v[4][8];
+// FP16 Omega straight into fragment order.  A workgroup owns one 32-row
+// block of the contraction and four 16-column tiles (64 columns: 4 KiB of
+// fragments, contiguous in memory); each of its 256 threads runs two Philox
+// blocks (one row, four consecutive columns each), places the 8 values in
+// LDS at their fragment positions, and the workgroup then writes the 4 KiB
+// with one 16-byte store per thread.
+__global__ __launch_bounds__(256) void omega_packed_f16_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
+                                                               int64_t n, int64_t r, uint16_t* dst,
+                                                               int64_t kb_count, int64_t nt_count) {
+    __shared__ uint16_t frag[4 * 64 * 8];
+    const int64_t groups = nt_count / 4;                       // 4-tile groups per 32-row block
+    const int64_t kb = blockIdx.x / groups, ntg = blockIdx.x % groups;
+    const int tid = threadIdx.x;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t row = kb * kKBlock + frag_slot(g, e);
-            if (row < n) {
-                const Words w = philox4x64_10((uint64_t)row, (uint64_t)(nt * 4 + c4), stream_id, 0,
-                                              seed, 0);
+    for (int h = 0; h < 2; ++h) {
+        const int pair = tid + 256 * h;                        // (rho, kappa): row in block, 4-column group
+        const int rho = pair >> 4, kappa = pair & 15;
+        const int64_t row = kb * kKBlock + rho;
+        const int64_t j4 = ntg * 16 + kappa;                   // global 4-column group
+        uint16_t v[4] = {0, 0, 0, 0};
+        if (row < n && 4 * j4 < r) {
+            const Words w = philox4x64_10((uint64_t)row, (uint64_t)j4, stream_id, 0, seed, 0);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int64_t col = nt * kNTile + 4 * c4 + c;
-                    v[c][e] = col < r ? f16_bits_from_word(w.x[c], t) : (uint16_t)0;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v[c][e] = 0;
-            }
+            for (int c = 0; c < 4; ++c) v[c] = 4 * j4 + c < r ? f16_bits_from_word(w.x[c], t) : (uint16_t)0;
         }
+        // slot rho -> (g, e): rho = 4g + e (e < 4) or 16 + 4g + (e - 4)
+        const int g = (rho & 15) >> 2, e = (rho & 3) + (rho >= 16 ? 4 : 0);
+        const int f = kappa >> 2;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int lane = 16 * g + 4 * c4 + c;
-            uint4 packed;
-            packed.x = v[c][0] | ((uint32_t)v[c][1] << 16);
-            packed.y = v[c][2] | ((uint32_t)v[c][3] << 16);
-            packed.z = v[c][4] | ((uint32_t)v[c][5] << 16);
-            packed.w = v[c][6] | ((uint32_t)v[c][7] << 16);
-            *reinterpret_cast<uint4*>(dst + (frag * 64 + lane) * 8) = packed;
-        }
+        for (int c = 0; c < 4; ++c) frag[(f * 64 + 16 * g + 4 * (kappa & 3) + c) * 8 + e] = v[c];
     }
+    __syncthreads();
+    const uint4 out = reinterpret_cast<const uint4*>(frag)[tid];
+    reinterpret_cast<uint4*>(dst + (kb * nt_count + ntg * 4) * 64 * 8)[tid] = out;
 }
 
 __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
@@ -297,11 +294,12 @@ hipError_t launch_omega_rowmajor(const OmegaTables& t, uint64_t seed, uint32_t s
 
 hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s) {
-    const int64_t total = dst.kb_count * dst.nt_count * 16;
-    if (total == 0) return hipSuccess;
-    const int block = 256, grid = grid_for(total, block);
-    hipLaunchKernelGGL(omega_packed_f16_kernel, dim3(grid), dim3(block), 0, s, t, seed, stream_id,
-                       n, r, static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count);
+    if (dst.kb_count == 0 || dst.nt_count == 0) return hipSuccess;
+    if (dst.nt_count % 4 != 0) return hipErrorInvalidValue;   // column blocks of 128 or 256
+    const int64_t blocks = dst.kb_count * (dst.nt_count / 4);
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(omega_packed_f16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, seed, stream_id, n, r,
+                       static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count);
     return hipGetLastError();
 }
 
