@@ -186,8 +186,9 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
  *     Q = QR(Y);  B = Q^T A;  U', S, V' = SVD(B);  U = Q U'[:, :k].
  * Omega is generated from (seed, stream_id 0) in omega_type and the
  * projection runs with `algo` (RP_ALGO_SPLIT_F16 is the paper's method;
- * RP_ALGO_F32 the baseline); the other products are FP32 with FP64
- * accumulation.  Every QR is CholeskyQR2 with the Gram matrix, Cholesky
+ * RP_ALGO_F32 the baseline); A^T Q (power scheme and B) is a plain FP32
+ * library GEMM (rocBLAS), the other products FP32 with FP64 accumulation.
+ * Every QR is CholeskyQR2 with the Gram matrix, Cholesky
  * factor and triangular inverse in FP64; the SVD of B is taken as
  * B^T = Q_B R_B (CholeskyQR2) followed by a one-sided Jacobi SVD of R_B^T in
  * FP64.

@@ -263,6 +263,12 @@ int small_grid(int64_t total) {
 
 }  // namespace
 
+// Projections with r <= RPMI_NARROW_MAX use the 128-column tile (several
+// column tiles when r > 128); the packed Omega is padded to 128 columns for
+// r <= 128 and to 256 beyond.
+#ifndef RPMI_NARROW_MAX
+#define RPMI_NARROW_MAX 128
+#endif
 int64_t split_f16_col_block(int64_t r) { return r <= 128 ? 128 : 256; }
 int64_t f32_col_block() { return F32Tile::BN; }
 int64_t proj_k_block() { return 64; }   // multiple of every tile's step (SplitTile 64, DmaTile 32, F32Tile 32)
@@ -291,7 +297,7 @@ SplitPlan plan_for(int64_t m, int64_t n, int64_t r, int num_cus) {
 }
 
 SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
-    return r <= 128 ? plan_for<NarrowCfg>(m, n, r, num_cus) : plan_for<WideCfg>(m, n, r, num_cus);
+    return r <= RPMI_NARROW_MAX ? plan_for<NarrowCfg>(m, n, r, num_cus) : plan_for<WideCfg>(m, n, r, num_cus);
 }
 
 int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
@@ -323,7 +329,8 @@ hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
-    return a.r <= 128 ? launch_split_with<NarrowCfg, SplitTile128>(a, s) : launch_split_with<WideCfg, SplitTile>(a, s);
+    return a.r <= RPMI_NARROW_MAX ? launch_split_with<NarrowCfg, SplitTile128>(a, s)
+                                  : launch_split_with<WideCfg, SplitTile>(a, s);
 }
 
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {

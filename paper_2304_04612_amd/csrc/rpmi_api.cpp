@@ -13,6 +13,8 @@
 #include "../../include/rpmi.h"
 #include "rpmi_internal.h"
 
+#include <rocblas/rocblas.h>
+
 struct rp_ctx_s {
     int device = 0;
     uint64_t* d_thresholds = nullptr;
@@ -42,6 +44,7 @@ struct rp_ctx_s {
     rpmi::JacobiProb* graph_jtab = nullptr;   // the batched Jacobi table read by the graph
     size_t graph_jtab_entries = 0;
     std::unordered_map<uint64_t, double> tuned_scale;
+    rocblas_handle blas = nullptr;         // plain FP32 GEMMs of rsvd (created on first use)
 };
 
 namespace {
@@ -190,6 +193,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
     if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
     delete ctx;
     return RP_OK;
 }
@@ -711,15 +715,36 @@ rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) 
 // (re-orthonormalised), then Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B with R_B^T
 // left in w.MW.  Launches kernels and device-to-device copies only
 // (capturable in a graph).
+// Z = A^T Q (n x p, row-major) for A (m x n, lda) and Q (m x p): with
+// `blas`, the library FP32 GEMM (column-major view: Z^T = Q^T A, p x n);
+// otherwise the FP64-accumulating GEMM (capturable, no library state).
+rp_status gemm_at_q(rp_ctx ctx, bool blas, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda,
+                    const float* Q, float* Z, hipStream_t s) {
+    if (blas) {
+        if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
+            return fail(ctx, RP_ERR_HIP, "rocblas_create_handle failed");
+        if (rocblas_set_stream(ctx->blas, s) != rocblas_status_success)
+            return fail(ctx, RP_ERR_HIP, "rocblas_set_stream failed");
+        const float one = 1.0f, zero = 0.0f;
+        if (rocblas_sgemm(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)p,
+                          (rocblas_int)n, (rocblas_int)m, &one, Q, (rocblas_int)p, A, (rocblas_int)lda, &zero, Z,
+                          (rocblas_int)p) != rocblas_status_success)
+            return fail(ctx, RP_ERR_HIP, "rocblas_sgemm failed");
+        return RP_OK;
+    }
+    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
+    return RP_OK;
+}
+
 rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p, int32_t power_iters,
-                          float* Y, const RsvdScratch& w, hipStream_t s) {
+                          float* Y, const RsvdScratch& w, hipStream_t s, bool blas = false) {
     rp_status st;
     const int64_t m = q.m, n = q.n, lda = q.lda;
     const float* A = q.A;
     for (int32_t t = 0; t < power_iters; ++t) {
         if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Z = A^T Q (n x p)
-        RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
+        if ((st = gemm_at_q(ctx, blas, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
         if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Y = A W (FP32 x FP32): the FP32 projection kernel with W in fragment order
         RP_HIP(ctx, rpmi::launch_pack_omega(w.W, true, n, p, p, w.pkw, true, s));
@@ -728,7 +753,7 @@ rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& 
     // Algorithm 1 line 2: Q = QR(Y)
     if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
     // line 3: B^T = A^T Q (n x p)
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, w.Q, p, 1, 0.0, w.Z, p, 1, s)));
+    if ((st = gemm_at_q(ctx, blas, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
     // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
     return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, w.GP, s);
 }
@@ -745,11 +770,12 @@ rp_status rsvd_after_svd(rp_ctx ctx, const rp_rsvd_problem& q, int64_t p, const 
 }
 
 // The whole of Algorithm 1 after the projection, for one problem (the
-// Jacobi table entry is written with a stream-ordered host copy).
+// Jacobi table entry is written with a stream-ordered host copy; A^T Q by the
+// library FP32 GEMM).
 rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
                                 int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
-    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s)) != RP_OK) return st;
+    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s, true)) != RP_OK) return st;
     const rpmi::JacobiProb jp{w.MW, w.MV, (int)p, 0, w.jflags};
     RP_HIP(ctx, hipMemcpyAsync(w.jtab, &jp, sizeof jp, hipMemcpyHostToDevice, s));
     RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,
