@@ -147,3 +147,19 @@ def test_rsvd_batched_e4m3_omega():
     opt = np.sqrt(np.sum(np.linalg.svd(a.astype(np.float64), compute_uv=False)[20:] ** 2)) / np.linalg.norm(a)
     print(f"rank-20 relative error: f16 {errs['f16']:.4e}  e4m3 {errs['e4m3']:.4e}  optimum {opt:.4e}")
     assert errs["e4m3"] <= 1.5 * errs["f16"] and errs["f16"] <= 3.0 * opt
+
+
+def test_project_grouped_e4m3():
+    """Grouped projections with the e4m3 Omega: every Y within the
+    elementwise bound of the product with Omega8 / s_j (exact in FP16)."""
+    shapes = [(256, 2048, 96), (100, 1000, 160), (513, 640, 33)]
+    announce(f"grouped e4m3 {shapes}")
+    rng = np.random.default_rng(4)
+    mats = [rng.standard_normal((m, n)).astype(np.float32) for m, n, _ in shapes]
+    ys = rp().rp_project_grouped([(dev(a), r, 6, j) for j, (a, (_, _, r)) in enumerate(zip(mats, shapes))], "e4m3")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, (a, (m, n, r)) in enumerate(zip(mats, shapes)):
+        _, _, val = omega.omega_e4m3(6, j, n, r)
+        ref = a.astype(np.float64) @ val
+        bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, val)
+        assert np.all(np.abs(host(ys[j]).astype(np.float64) - ref) <= bound), j

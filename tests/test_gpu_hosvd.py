@@ -121,3 +121,19 @@ def test_hosvd_full_size_properties():
     # smallest projected signal singular value (~35), so part of the signal
     # leaks out of the captured subspaces: a few times the noise fraction
     assert e_split < 5.0 * frac
+
+
+def test_hosvd_e4m3_omega():
+    """RP-HOSVD with the e4m3 Omega_i (column-scaled FP8 values, exact in
+    FP16): same oracle comparison as the FP16 case."""
+    dims, core_dims = (48, 64, 40), (6, 5, 4)
+    announce(f"hosvd e4m3 dims={dims}")
+    rng = np.random.default_rng(17)
+    x = synth.np_tucker(dims, core_dims, rng)
+    g, qs, st = _gpu(x, core_dims, 23, "e4m3", "split_f16")
+    assert st == rp().RP_OK
+    oms = [omega.omega_e4m3(23, i, x.size // x.shape[i], core_dims[i])[2] for i in range(x.ndim)]
+    g_o, qs_o = ohosvd.rp_hosvd(x.astype(np.float64), oms)
+    for i, (q, q_o) in enumerate(zip(qs, qs_o)):
+        assert _rel(q, q_o) < 2e-4, i
+    assert _rel(ohosvd.reconstruct(g, qs), x.astype(np.float64)) < 5e-5
