@@ -286,6 +286,72 @@ __global__ void sum_partials_kernel(const double* __restrict__ part, int64_t cou
     }
 }
 
+// ---------------------------------------------------------------- C = A^T Q on FP32 MFMA
+// C (N x P, row-major, ldc) = A^T Q for A (K x N, row-major, lda) and Q
+// (K x P, row-major, ldq), FP32 products with FP32 accumulation on
+// v_mfma_f32_16x16x4f32 (lane 16g + c supplies A^T[c][g] and Q[g][c] of a
+// 16 x 4 / 4 x 16 step).  A wave owns 64 rows x 64 columns of C as 4 x 4
+// MFMA tiles with permuted rows and columns: row r of tile t is C row
+// 4r + t of the wave's block (columns alike), so that lane c reads the four
+// tiles' operands with one 16-byte load of 4 consecutive elements of a row
+// of A (of Q).  Four waves take four consecutive 64-row blocks.  Requires
+// lda, ldq, ldc multiples of 4 and 16-byte aligned A, Q and C.
+__global__ __launch_bounds__(256) void gemm_tn_f32_kernel(int64_t N, int64_t P, int64_t K, const float* __restrict__ A,
+                                                          int64_t lda, const float* __restrict__ Q, int64_t ldq,
+                                                          float* __restrict__ C, int64_t ldc) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t i0 = (blockIdx.x * 4 + wave) * 64, j0 = blockIdx.y * (int64_t)64;
+    const int64_t ia = i0 + 4 * c, jq = j0 + 4 * c;       // this lane's 4 rows of C (tiles 0..3), 4 columns
+    const bool a_full = ia + 3 < N, q_full = jq + 3 < P;
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    auto load4 = [](const float* row, int64_t col, int64_t lim, bool full) -> f4 {
+        if (full) return *reinterpret_cast<const f4*>(row + col);
+        f4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = col + e < lim ? row[col + e] : 0.0f;
+        return v;
+    };
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        f4 av[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {                      // k = k0 + 4u + g
+            const int64_t k = k0 + 4 * u + g;
+            const bool in = k < K;
+            av[u] = in ? load4(A + k * lda, ia, N, a_full) : f4{0.f, 0.f, 0.f, 0.f};
+            qv[u] = in ? load4(Q + k * ldq, jq, P, q_full) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
+    }
+    // lane (g, c) holds D[4g + e][c] of tile (a, b): C row i0 + 4 (4g + e) + a, column j0 + 4c + b
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + 4 * (4 * g + e) + a;
+            if (i >= N) continue;
+            float* crow = C + i * ldc;
+            if (q_full) {
+                *reinterpret_cast<f4*>(crow + jq) = f4{acc[a][0][e], acc[a][1][e], acc[a][2][e], acc[a][3][e]};
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (jq + b < P) crow[jq + b] = acc[a][b][e];
+            }
+        }
+}
+
 // ---------------------------------------------------------------- parallel one-sided Jacobi
 // Many workgroups per round: one workgroup per column pair, one launch per
 // round of the round-robin (circle) ordering, so that a sweep streams the
@@ -585,6 +651,20 @@ hipError_t gram_acc64(int64_t p, int64_t K, const T* Y, int64_t ldy, double* G, 
 
 template hipError_t gram_acc64<float>(int64_t, int64_t, const float*, int64_t, double*, double*, int, hipStream_t);
 template hipError_t gram_acc64<double>(int64_t, int64_t, const double*, int64_t, double*, double*, int, hipStream_t);
+
+hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t lda, const float* Q, int64_t ldq,
+                       float* C, int64_t ldc, hipStream_t s) {
+    if (N <= 0 || P <= 0) return hipSuccess;
+    const bool ok = lda % 4 == 0 && ldq % 4 == 0 && ldc % 4 == 0 && ((uintptr_t)A & 15) == 0 &&
+                    ((uintptr_t)Q & 15) == 0 && ((uintptr_t)C & 15) == 0;
+    if (!ok)   // off the 16-byte path: the FP64-accumulating GEMM
+        return gemm_acc64<float, float, float>(N, P, K, 1.0, A, 1, lda, Q, ldq, 1, 0.0, C, ldc, 1, s);
+    const int64_t gx = (N + 255) / 256, gy = (P + 63) / 64;
+    if (gx > 0x7FFFFFFF || gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_tn_f32_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, N, P, K, A, lda, Q, ldq,
+                       C, ldc);
+    return hipGetLastError();
+}
 
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
                             double tol, unsigned int* status, hipStream_t s) {

@@ -717,7 +717,7 @@ rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) 
 // (capturable in a graph).
 // Z = A^T Q (n x p, row-major) for A (m x n, lda) and Q (m x p): with
 // `blas`, the library FP32 GEMM (column-major view: Z^T = Q^T A, p x n);
-// otherwise the FP64-accumulating GEMM (capturable, no library state).
+// otherwise this library's FP32 MFMA kernel (capturable, no library state).
 rp_status gemm_at_q(rp_ctx ctx, bool blas, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda,
                     const float* Q, float* Z, hipStream_t s) {
     if (blas) {
@@ -732,7 +732,7 @@ rp_status gemm_at_q(rp_ctx ctx, bool blas, int64_t m, int64_t n, int64_t p, cons
             return fail(ctx, RP_ERR_HIP, "rocblas_sgemm failed");
         return RP_OK;
     }
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(n, p, m, 1.0, A, 1, lda, Q, p, 1, 0.0, Z, p, 1, s)));
+    RP_HIP(ctx, rpmi::gemm_tn_f32(n, p, m, A, lda, Q, p, Z, p, s));
     return RP_OK;
 }
 
@@ -769,13 +769,16 @@ rp_status rsvd_after_svd(rp_ctx ctx, const rp_rsvd_problem& q, int64_t p, const 
     return RP_OK;
 }
 
+#ifndef RPMI_RSVD_BLAS
+#define RPMI_RSVD_BLAS 1
+#endif
 // The whole of Algorithm 1 after the projection, for one problem (the
 // Jacobi table entry is written with a stream-ordered host copy; A^T Q by the
 // library FP32 GEMM).
 rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
                                 int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
-    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s, true)) != RP_OK) return st;
+    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s, RPMI_RSVD_BLAS != 0)) != RP_OK) return st;
     const rpmi::JacobiProb jp{w.MW, w.MV, (int)p, 0, w.jflags};
     RP_HIP(ctx, hipMemcpyAsync(w.jtab, &jp, sizeof jp, hipMemcpyHostToDevice, s));
     RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,

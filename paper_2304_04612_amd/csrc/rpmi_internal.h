@@ -133,6 +133,10 @@ hipError_t gram_acc64(int64_t p, int64_t K, const T* Y, int64_t ldy, double* G, 
                       hipStream_t s);
 // dst[i][b][p] = src[b][i][p], src of shape [B, I, P] in C order
 hipError_t launch_swap01(const float* src, int64_t B, int64_t I, int64_t P, float* dst, hipStream_t s);
+// C (N x P) = A^T Q, A K x N and Q K x P row-major: FP32 MFMA with FP32
+// accumulation (FP64-accumulating fallback off the 16-byte path)
+hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t lda, const float* Q, int64_t ldq,
+                       float* C, int64_t ldc, hipStream_t s);
 hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, hipStream_t s);
 hipError_t launch_zero_upper(double* A, int64_t lda, int64_t p, hipStream_t s);
 hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t p, hipStream_t s);
