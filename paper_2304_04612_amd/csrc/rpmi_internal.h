@@ -9,7 +9,7 @@ namespace rpmi {
 
 // ---------------------------------------------------------------- Omega tables
 constexpr int kF16TableMax = 20000;   // threshold table capacity (18571 used)
-constexpr int kGuideLog2 = 12;        // guide table over the top 12 bits of u
+constexpr int kGuideLog2 = 16;        // guide table over the top 16 bits of u (256 KiB)
 constexpr int kGuideSize = (1 << kGuideLog2) + 1;
 
 struct OmegaTables {
