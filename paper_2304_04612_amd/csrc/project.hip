@@ -283,7 +283,10 @@ SplitPlan plan_for(int64_t m, int64_t n, int64_t r, int num_cus) {
     const int64_t tiles = ((m + T::BM - 1) / T::BM) * ((r + T::BN - 1) / T::BN);
     const int64_t nfull = n / T::BK;
     if (tiles <= 0 || nfull <= 0) return plan;
-    int64_t k = num_cus / tiles;                 // fill the chip with tiles x k workgroups
+#ifndef RPMI_CU_OVERSUB
+#define RPMI_CU_OVERSUB 1
+#endif
+    int64_t k = RPMI_CU_OVERSUB * num_cus / tiles;   // fill the chip with tiles x k workgroups
 #ifndef RPMI_KSPLIT_MAX
 #define RPMI_KSPLIT_MAX 64
 #endif

@@ -906,7 +906,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     Arena ar;
     std::vector<size_t> o_pk(count), o_y(count);
     std::vector<rpmi::PackedOmega> pk(count);
-    int64_t mm = 0, mn = 0, mk = 0, mp = 0;
+    int64_t mp = 0;
     size_t raw = 0;
     for (int32_t g = 0; g < count; ++g) {
         const rp_rsvd_problem& q = probs[g];
@@ -914,7 +914,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         pk[g] = packed_geometry(q.n, p, algo, nullptr);
         o_pk[g] = ar.take(packed_bytes(pk[g], algo));
         o_y[g] = ar.take((size_t)q.m * p * 4);
-        mm = q.m > mm ? q.m : mm; mn = q.n > mn ? q.n : mn; mk = q.k > mk ? q.k : mk; mp = p > mp ? p : mp;
+        mp = p > mp ? p : mp;
         raw = raw_bytes(omega_type, algo, q.n, p) > raw ? raw_bytes(omega_type, algo, q.n, p) : raw;
     }
     const size_t o_raw = ar.take(raw);
@@ -928,7 +928,6 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     char* base = static_cast<char*>(ctx->ws);
     for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
     for (int32_t g = 0; g < count; ++g) ws[g].bind(base + o_ws[g]);
-    (void)mm; (void)mn; (void)mk;
 
     // projections of the 16-byte-path problems go out grouped
     std::vector<rpmi::ProjArgs> grouped;
