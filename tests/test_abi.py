@@ -13,7 +13,9 @@ HEADER = os.path.join(ROOT, "include", "rpmi.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rp_[a-z0-9_]+)\s*\(", text)))
+    # every function declaration: a return type (rp_status or const char*)
+    # followed by the name and its parameter list
+    return sorted(set(re.findall(r"^(?:rp_status|const\s+char\s*\*)\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +29,8 @@ def L():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for n in ("rp_create", "rp_destroy", "rp_project", "rp_omega_generate", "rp_get_device_status"):
+    for n in ("rp_create", "rp_destroy", "rp_project", "rp_omega_generate", "rp_get_device_status", "rsvd",
+              "rsvd_batched", "rp_hosvd", "rp_project_grouped", "rp_omega_generate_e4m3"):
         assert n in names
 
 
