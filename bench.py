@@ -160,7 +160,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32 via split fp16 MFMA, fp32 accumulate",
+        "dtype": "f16",
+        "dtype_note": "FP32 A split into FP16 hi + 2^-11 lo in registers; FP16 MFMA products, FP32 accumulation",
         "data": "synthetic",
         "config": {"workload": "projection Y=A*Omega, A 16384x16384 FP32 (sigma_i=10^(-6i/16384), "
                                "Haar U,V), Omega 16384x256 FP16 (Philox4x64 + exact FP16 inverse CDF)",
