@@ -15,9 +15,11 @@
 // * Inverse of a lower-triangular L: blocked; diagonal blocks inverted in LDS,
 //   off-diagonal blocks X_ij = -X_ii (sum_{j<=l<i} L_il X_lj) row block by row
 //   block with gemm_acc64.
-// * One-sided Jacobi SVD of a small square matrix in one workgroup
-//   (round-robin pair ordering, rotation angles from the 2x2 Gram of each
-//   column pair, de Rijk's convergence test on the relative off-diagonal).
+// * One-sided Jacobi SVD of a small square matrix, parallel over column
+//   pairs (round-robin ordering, one launch per round, rotation angles from
+//   the 2x2 Gram of each pair, convergence when no pair has a relative
+//   off-diagonal above the tolerance in a whole sweep).
+// * C = A^T Q on FP32 MFMA; Gram products split along the contraction.
 #include "rpmi_internal.h"
 
 namespace rpmi {
@@ -204,78 +206,6 @@ __global__ void zero_upper_kernel(double* A, int64_t lda, int64_t p) {
     }
 }
 
-// ----------------------------------------------------------------- Jacobi SVD
-// One-sided Jacobi on the columns of W (n x n, FP64, row-major, ld = n) in one
-// workgroup; V (n x n) accumulates the rotations.  On return the columns of W
-// are mutually orthogonal: W_in V = W_out.  Converged when every pair
-// satisfies |w_i . w_j| <= tol sqrt(|w_i|^2 |w_j|^2); sets NOT_CONVERGED after
-// max_sweeps otherwise.
-__global__ __launch_bounds__(1024) void jacobi_svd_kernel(double* W, double* V, int n, int max_sweeps,
-                                                          double tol, unsigned int* status) {
-    const int tid = threadIdx.x;
-    __shared__ int rotated;
-    __shared__ int perm[1025];
-    for (int e = tid; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-    const int m = n + (n & 1);                 // even count for round-robin (a dummy if odd)
-    for (int i = tid; i < m; i += blockDim.x) perm[i] = i;
-    __syncthreads();
-    const int pairs = m / 2;
-    // threads per pair: a power of two <= blockDim / pairs (>= 1)
-    int tpp = 1;
-    while (tpp * 2 * pairs <= (int)blockDim.x && tpp < 64) tpp *= 2;
-    const int pair = tid / tpp, sub = tid % tpp;
-    bool converged = false;
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-        if (tid == 0) rotated = 0;
-        __syncthreads();
-        for (int round = 0; round < m - 1; ++round) {
-            for (int pr = pair; pr < pairs; pr += blockDim.x / tpp) {
-                int a = perm[pr], bb = perm[m - 1 - pr];
-                if (a > bb) { const int t = a; a = bb; bb = t; }
-                const bool live = bb < n && pr < pairs;
-                double alpha = 0.0, beta = 0.0, gamma = 0.0;
-                if (live) {
-                    for (int r = sub; r < n; r += tpp) {
-                        const double x = W[r * n + a], y = W[r * n + bb];
-                        alpha += x * x; beta += y * y; gamma += x * y;
-                    }
-                }
-                // reduce within the tpp lanes of this pair (contiguous lanes)
-                for (int off = tpp / 2; off > 0; off /= 2) {
-                    alpha += __shfl_xor(alpha, off, tpp);
-                    beta += __shfl_xor(beta, off, tpp);
-                    gamma += __shfl_xor(gamma, off, tpp);
-                }
-                if (live && fabs(gamma) > tol * sqrt(alpha * beta) && gamma != 0.0) {
-                    // rotation zeroing the (a, bb) entry of the 2x2 Gram
-                    const double zeta = (beta - alpha) / (2.0 * gamma);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                    for (int r = sub; r < n; r += tpp) {
-                        const double x = W[r * n + a], y = W[r * n + bb];
-                        W[r * n + a] = cs * x - sn * y;
-                        W[r * n + bb] = sn * x + cs * y;
-                        const double vx = V[r * n + a], vy = V[r * n + bb];
-                        V[r * n + a] = cs * vx - sn * vy;
-                        V[r * n + bb] = sn * vx + cs * vy;
-                    }
-                    if (sub == 0) rotated = 1;
-                }
-            }
-            __syncthreads();
-            // round-robin: keep position 0, rotate the rest
-            if (tid == 0) {
-                const int last = perm[m - 1];
-                for (int i = m - 1; i > 1; --i) perm[i] = perm[i - 1];
-                perm[1] = last;
-            }
-            __syncthreads();
-        }
-        converged = rotated == 0;
-        __syncthreads();
-    }
-    if (!converged && tid == 0) atomicOr(status, kStatusNotConverged);
-}
 
 // G = sum over z of the split partials, in the fixed order z = 0, 1, ...
 __global__ void sum_partials_kernel(const double* __restrict__ part, int64_t count, int nsplit, double* __restrict__ G) {
@@ -616,13 +546,6 @@ hipError_t launch_swap01(const float* src, int64_t B, int64_t I, int64_t P, floa
 hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s) {
     hipLaunchKernelGGL(trtri_apply_diag_kernel, dim3((unsigned)((r0 + NB - 1) / NB)), dim3(256), 0, s, X, ldx, r0,
                        (int)rows);
-    return hipGetLastError();
-}
-
-hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, unsigned int* status,
-                      hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, W, V, n, max_sweeps, tol, status);
     return hipGetLastError();
 }
 

@@ -141,8 +141,6 @@ hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, 
 hipError_t launch_zero_upper(double* A, int64_t lda, int64_t p, hipStream_t s);
 hipError_t trtri_lower(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t p, hipStream_t s);
 hipError_t launch_trtri_apply_diag(double* X, int64_t ldx, int64_t r0, int64_t rows, hipStream_t s);
-hipError_t jacobi_svd(double* W, double* V, int n, int max_sweeps, double tol, unsigned int* status,
-                      hipStream_t s);
 // One square problem of the parallel one-sided Jacobi SVD: W (n x n,
 // row-major in and out) becomes W V with orthogonal columns; pair_start = sum
 // of ceil(n/2) over the problems before it; flags: 4 ints of device scratch.
