@@ -285,8 +285,9 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
  * in runs of a multiple of 64 elements, the last mode among them, is first
  * copied mode-first into workspace).  Each QR is CholeskyQR2 (FP64 Gram,
  * Cholesky and triangular inverse), so Q_i is the orthonormal factor with a
- * positive-diagonal R.  The core contractions are FP32 products with FP64
- * accumulation, one mode at a time.
+ * positive-diagonal R.  The core is contracted one mode at a time: the first
+ * mode with FP32 MFMA products and FP32 accumulation, the others with FP64
+ * accumulation.
  * Outputs (device): core, C order J_0 x ... x J_{ndim-1} FP32; factors is a
  * host array of ndim device pointers, factors[i] dims[i] x J_i row-major FP32.
  * dims, ranks, factors: host arrays owned by the caller, read during the call.

@@ -1245,7 +1245,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
             RP_OK)
             return st;
     // core g = X x_1 Q_1^T ... x_N Q_N^T, one mode at a time: T has shape
-    // [lead, I_i, after_i]; out[b][j][p] = sum_k Q_i[k][j] T[b][k][p]
+    // [lead, I_i, after_i]; out[b][j][p] = sum_k Q_i[k][j] T[b][k][p] (the
+    // first mode on FP32 MFMA, the others with FP64 accumulation)
     const float* T = X;
     float* bufs[2] = {reinterpret_cast<float*>(base + o_t0), reinterpret_cast<float*>(base + o_t1)};
     int64_t lead = 1;
@@ -1255,6 +1256,9 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
         if (P == 1) {
             RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(lead, J, I, 1.0, T, I, 1, factors[i], J, 1, 0.0, out, J,
                                                                 1, s)));
+        } else if (lead == 1) {
+            // out (J x P) = Q_i^T T: the A^T Q form on FP32 MFMA
+            RP_HIP(ctx, rpmi::gemm_tn_f32(J, P, I, factors[i], J, T, P, out, P, s));
         } else {
             RP_HIP(ctx, (rpmi::gemm_acc64_batched<float, float, float>(J, P, I, 1.0, factors[i], 1, J, 0, T, P, 1,
                                                                         I * P, 0.0, out, P, 1, J * P, lead, s)));
