@@ -45,7 +45,14 @@ typedef enum rp_status {
     RP_ERR_NOT_SPD = 4,       /* device: Cholesky breakdown in CholeskyQR2        */
     RP_ERR_NOT_CONVERGED = 5, /* device: Jacobi SVD did not converge              */
     RP_ERR_NOMEM = 6,         /* device allocation failed                          */
-    RP_ERR_HIP = 7            /* a HIP runtime call failed (see rp_last_error)    */
+    RP_ERR_HIP = 7,           /* a HIP runtime call failed (see rp_last_error)    */
+    RP_ERR_OMEGA_RANGE = 8    /* device: a caller-supplied Omega packed for the
+                                 split-FP16 kernels holds an entry with
+                                 |omega| >= 32 or a non-finite one (the kernels
+                                 take the hi product against 2^11 Omega, exact
+                                 in FP16 only below 32; the generated Gaussian
+                                 never exceeds 9.1), or an e4m3 column scale
+                                 that is not a power of two in [2^-7, 2^15]     */
 } rp_status;
 
 /* Storage format of Omega (Sec. 3: a Gaussian matrix tolerates a short mantissa). */
@@ -130,20 +137,35 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
  *   r          number of columns of Omega and Y (r >= 0).
  *   omega_type storage format of Omega.
  *   seed, stream_id  used when omega == NULL: Omega is generated exactly as
- *              rp_omega_generate would, into context-owned workspace.
- *   omega, ldo a caller-supplied Omega (n x r row-major; FP16 bits or FP32
- *              according to omega_type), or NULL.
- *   algo       RP_ALGO_SPLIT_F16 (needs RP_OMEGA_F16) or RP_ALGO_F32.
- * With RP_ALGO_SPLIT_F16 an element of A that overflows FP16, or a non-finite
- * element, sets RP_ERR_RANGE in the device status word; Y is then unspecified
- * (a NaN element leaves NaN in its own row of Y).
+ *              rp_omega_generate (rp_omega_generate_e4m3 for RP_OMEGA_E4M3)
+ *              would, into context-owned workspace.
+ *   omega, ldo a caller-supplied Omega (n x r row-major: FP16 bits, FP32, or
+ *              e4m3fn bytes according to omega_type), or NULL.
+ *   col_scale  with a caller e4m3 Omega: r floats s_j (device), the power-of-
+ *              two column scales of rp_omega_generate_e4m3; the projection
+ *              takes Omega8[i][j] / s_j (exact in FP16 for s_j in
+ *              [2^-7, 2^15]).  Ignored otherwise (may be NULL).
+ *   algo       RP_ALGO_SPLIT_F16 (needs an FP16 or e4m3 Omega) or RP_ALGO_F32.
+ *   a_scale_exp  s: the split takes 2^s A instead of A and the epilogue
+ *              multiplies by 2^-s (both exact while 2^s A and Y stay inside
+ *              the FP32 normal range), so that an A whose magnitudes exceed
+ *              the FP16 range (Sec. 4.2) can be brought inside it; 0 = off.
+ *              |s| <= 64.  Ignored by RP_ALGO_F32.
+ * With RP_ALGO_SPLIT_F16 an element of 2^s A that overflows FP16 (finite
+ * |2^s a| >= 65520), or a non-finite element, sets RP_ERR_RANGE in the device
+ * status word; Y is then unspecified (a NaN element leaves NaN in its own
+ * row of Y).  A caller FP16 or e4m3 Omega is scanned on the device: when it
+ * holds an entry with |omega| >= 32 the call takes the kernel with two
+ * accumulators (eq:shgemm-3 as written), which has no such bound; the scan
+ * is read back once, so such a call synchronises `stream`.
  * m, n or r equal to zero is allowed (n == 0 writes Y = 0).
  * May grow the context workspace (device allocation, which synchronises the
  * device when it happens).
  */
 rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r,
                      rp_omega_t omega_type, uint64_t seed, uint32_t stream_id,
-                     const void* omega, int64_t ldo, rp_algo_t algo,
+                     const void* omega, int64_t ldo, const float* col_scale,
+                     rp_algo_t algo, int32_t a_scale_exp,
                      float* Y, int64_t ldy, void* stream);
 
 /*
@@ -151,30 +173,37 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r,
  * Omega across many projections (e.g. the RSVD of many matrices sharing n and
  * r).  rp_omega_packed_size() gives the byte size of the buffer for (n, r,
  * algo) in *bytes (host pointer).  rp_omega_pack() fills `packed` (device,
- * caller-owned, that many bytes) from `omega` (n x r row-major, FP16 bits or
- * FP32 by `type`) or, when omega == NULL, by generating Omega for
- * (seed, stream_id) exactly as rp_omega_generate() does.  The split-FP16
- * algorithm takes FP16 fragments (type must be RP_OMEGA_F16); the FP32
- * algorithm takes FP32 fragments (an FP16 Omega is widened exactly).
- * Zero padding beyond n rows and r columns is part of the packed buffer.
+ * caller-owned, that many bytes) from `omega` (n x r row-major: FP16 bits,
+ * FP32, or e4m3fn bytes with col_scale, by `type`) or, when omega == NULL, by
+ * generating Omega for (seed, stream_id) exactly as rp_omega_generate() (or
+ * rp_omega_generate_e4m3()) does.  The split-FP16 algorithm takes FP16
+ * fragments (type RP_OMEGA_F16, or RP_OMEGA_E4M3 whose values Omega8 / s_j
+ * are exact in FP16); the FP32 algorithm takes FP32 fragments (an FP16 or
+ * e4m3 Omega is widened exactly).  col_scale: r floats (device) for a caller
+ * e4m3 Omega, else ignored.  Packing a caller Omega for the split-FP16
+ * algorithm records RP_ERR_OMEGA_RANGE in the device status word if an entry
+ * has |omega| >= 32 or is not finite (or a column scale is not a power of two
+ * in [2^-7, 2^15]); rp_project_packed() then leaves Y unspecified (rp_project()
+ * handles such an Omega).  Zero padding beyond n rows and r columns is part
+ * of the packed buffer.
  */
 rp_status rp_omega_packed_size(int64_t n, int64_t r, rp_algo_t algo, size_t* bytes);
 rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void* omega,
-                        int64_t ldo, rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
-                        void* packed, void* stream);
+                        int64_t ldo, const float* col_scale, rp_omega_t type, int64_t n, int64_t r,
+                        rp_algo_t algo, void* packed, void* stream);
 
 /*
  * Y = A * Omega with Omega already packed by rp_omega_pack() for the same
  * (n = A->cols, r, algo).  Launches one projection kernel (none if m or r is
- * 0; a fill kernel if n is 0).  Same layout rules and device status as
- * rp_project().  When the output tiles of the split-FP16 path do not fill the
- * device, the contraction is split across workgroups whose partial sums live
- * in a context-owned workspace; growing it (first use of a shape) allocates
- * and synchronises the device.  Launches that share a context must not run
- * concurrently on different streams.
+ * 0; a fill kernel if n is 0).  Same layout rules, a_scale_exp and device
+ * status as rp_project().  When the output tiles of the split-FP16 path do
+ * not fill the device, the contraction is split across workgroups whose
+ * partial sums live in a context-owned workspace; growing it (first use of a
+ * shape) allocates and synchronises the device.  Launches that share a
+ * context must not run concurrently on different streams.
  */
 rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
-                            rp_algo_t algo, float* Y, int64_t ldy, void* stream);
+                            rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy, void* stream);
 
 /*
  * Randomized SVD (Algorithm 1, Sec. 2.2) of the m x n FP32 matrix A (row-major,
@@ -194,15 +223,29 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
  * FP64.
  * Outputs (device): U m x k (ldu >= k), S k doubles in descending order, VT
  * k x n (ldvt >= n).  Singular vectors are determined up to sign.
+ * a_scale_exp applies to the projection Y = A Omega as in rp_project().
  * Device conditions: RP_ERR_NOT_SPD (a Cholesky pivot was not positive:
  * Y numerically rank-deficient beyond FP64 Gram range), RP_ERR_NOT_CONVERGED
- * (Jacobi), RP_ERR_RANGE (split path, A outside FP16 range).  Allocates or
- * grows the context workspace as needed (synchronising the device then).
+ * (Jacobi), RP_ERR_RANGE (split path, 2^s A outside FP16 range).
+ * Workspace: with work == NULL the context workspace is used and grown as
+ * needed (allocating and synchronising the device then).  Otherwise `work`
+ * (device, caller-owned, 256-byte aligned, contents undefined on entry) must
+ * hold at least the bytes rsvd_workspace_size() reports for the same
+ * arguments; the call then allocates nothing and does not synchronise, and
+ * the caller keeps `work` alive until the work on `stream` has finished.
  */
 rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
                int64_t k, int64_t oversample, int32_t power_iters,
-               uint64_t seed, rp_omega_t omega_type, rp_algo_t algo,
-               float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* stream);
+               uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, int32_t a_scale_exp,
+               float* U, int64_t ldu, double* S, float* VT, int64_t ldvt,
+               void* work, size_t work_bytes, void* stream);
+
+/*
+ * Bytes of caller workspace rsvd() needs for these arguments (host pointer
+ * `bytes`).  Validates the arguments as rsvd() does, apart from pointers.
+ */
+rp_status rsvd_workspace_size(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64_t oversample,
+                              int32_t power_iters, rp_omega_t omega_type, rp_algo_t algo, size_t* bytes);
 
 /*
  * e4m3 Omega (the low-precision storage of Sec. 3 with the OCP FP8 E4M3FN
@@ -211,15 +254,17 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
  * column) and Omega8[i][j] = sat448(RNE_e4m3(w[i][j] s_j)), so that
  * A Omega8[:, j] / s_j approximates A w[:, j].  omega: n x r e4m3fn bytes
  * (ldo >= r); col_scale: r floats s_j.  Device, caller-owned.  The projection
- * entry points take RP_OMEGA_E4M3 only for a generated Omega: they use the
- * values Omega8 / s_j, which are exact in FP16.
+ * entry points use the values Omega8 / s_j, which are exact in FP16; they
+ * take this Omega either generated (omega == NULL) or from the caller with
+ * its col_scale.
  */
 rp_status rp_omega_generate_e4m3(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64_t n, int64_t r,
                                  uint8_t* omega, int64_t ldo, float* col_scale, void* stream);
 
 /*
- * One projection of a grouped call: Y = A Omega with Omega (A.cols x r, FP16)
- * generated from (seed, stream_id).  A, Y: device, caller-owned.
+ * One projection of a grouped call: Y = A Omega with Omega (A.cols x r, FP16
+ * or e4m3) generated from (seed, stream_id).  A, Y: device, caller-owned.
+ * a_scale_exp as in rp_project().
  */
 typedef struct {
     rp_desc A;
@@ -228,6 +273,7 @@ typedef struct {
     uint32_t stream_id;
     float* Y;
     int64_t ldy;
+    int32_t a_scale_exp;
 } rp_project_problem;
 
 /*
@@ -271,7 +317,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                        uint64_t seed, rp_omega_t omega_type, void* stream);
 
 /*
- * Random-projection HOSVD (Algorithm 2, Sec. 2.3) of the ndim-way FP32 tensor
+ * Random-projection HOSVD (Algorithm 2, Sec. 5.2) of the ndim-way FP32 tensor
  * X (C order, dims[0] x ... x dims[ndim-1], 2 <= ndim <= 8), with target
  * ranks J_i = ranks[i] (oversampling included; 1 <= J_i <= dims[i],
  * J_i <= prod_{l != i} dims[l], J_i <= 1024):

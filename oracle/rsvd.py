@@ -55,17 +55,3 @@ def residual_qqta(a, q):
 def halko_bound(sigma_tail_fro, p, s):
     """Right-hand side of eq:qqta-acc: sqrt(1 + p/(s-1)) ||Sigma_2||_F."""
     return float(np.sqrt(1.0 + p / (s - 1.0)) * sigma_tail_fro)
-
-
-def sign_normalise(u, vt=None):
-    """Fix the sign of each singular pair so that the largest-|.| entry of
-    each column of U is positive (singular vectors are unique up to sign)."""
-    u = np.array(u, np.float64, copy=True)
-    idx = np.argmax(np.abs(u), axis=0)
-    sgn = np.sign(u[idx, np.arange(u.shape[1])])
-    sgn[sgn == 0] = 1.0
-    u *= sgn[None, :]
-    if vt is None:
-        return u
-    vt = np.array(vt, np.float64, copy=True) * sgn[:, None]
-    return u, vt

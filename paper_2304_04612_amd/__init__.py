@@ -20,6 +20,7 @@ RP_ERR_NOT_SPD = 4
 RP_ERR_NOT_CONVERGED = 5
 RP_ERR_NOMEM = 6
 RP_ERR_HIP = 7
+RP_ERR_OMEGA_RANGE = 8
 
 RP_OMEGA_F32 = 0
 RP_OMEGA_F16 = 1
@@ -45,7 +46,7 @@ class rp_desc(ctypes.Structure):
 
 class rp_project_problem(ctypes.Structure):
     _fields_ = [("A", rp_desc), ("r", ctypes.c_int64), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
-                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64)]
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64), ("a_scale_exp", ctypes.c_int32)]
 
 
 class rp_rsvd_problem(ctypes.Structure):
@@ -72,22 +73,27 @@ def lib():
         "rp_status_string": [i32],
         "rp_last_error": [vp],
         "rp_omega_generate": [vp, u64, u32, i64, i64, i32, vp, i64, vp],
-        "rp_project": [vp, ctypes.POINTER(rp_desc), i64, i32, u64, u32, vp, i64, i32, vp, i64, vp],
+        "rp_project": [vp, ctypes.POINTER(rp_desc), i64, i32, u64, u32, vp, i64, vp, i32, i32, vp, i64, vp],
         "rp_split_f16": [vp, vp, i64, vp, vp, vp],
         "rp_omega_packed_size": [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
-        "rp_omega_pack": [vp, u64, u32, vp, i64, i32, i64, i64, i32, vp, vp],
-        "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, vp, i64, vp],
+        "rp_omega_pack": [vp, u64, u32, vp, i64, vp, i32, i64, i64, i32, vp, vp],
+        "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, i32, vp, i64, vp],
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
-        "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, vp, i64, vp, vp, i64, vp],
+        "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, i32, vp, i64, vp, vp, i64, vp,
+                 ctypes.c_size_t, vp],
+        "rsvd_workspace_size": [vp, i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "rp_hosvd": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
         "rp_project_grouped": [vp, i32, vp, i32, vp],
         "rp_omega_generate_e4m3": [vp, u64, u32, i64, i64, vp, i64, vp, vp],
         "rsvd_batched": [vp, i32, vp, i32, u64, i32, vp],
+        "rpmi_build_f16_thresholds": [vp, i32],
+        "rpmi_build_guide": [vp, i32, vp, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_char_p if name in ("rp_status_string", "rp_last_error") else i32
+    L.rpmi_build_guide.restype = None
     _lib = L
     return L
 
@@ -175,10 +181,11 @@ def rp_omega_generate(n, r, seed, stream_id=0, omega="f16", out=None, ctx=None):
 
 
 def rp_project(a, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo="split_f16",
-               y=None, desc=None, ctx=None):
+               y=None, desc=None, col_scale=None, a_scale_exp=0, ctx=None):
     """Y = A Omega.  ``a``: float32 CUDA tensor (or ``desc`` for an unfolding
     layout, with ``a`` keeping the storage alive).  ``omega``: optional
-    caller-supplied Omega (int16 FP16 bits or float32, n x r)."""
+    caller-supplied Omega (int16 FP16 bits, float32, or uint8 e4m3 codes with
+    ``col_scale``, n x r).  ``a_scale_exp``: s, the split takes 2^s A."""
     import torch
     ctx = ctx or default_context()
     d = desc if desc is not None else desc_from_tensor(a)
@@ -187,8 +194,8 @@ def rp_project(a, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo="sp
     ldy = y.stride(0) if y.numel() else max(r, 1)
     ldo = omega.stride(0) if omega is not None and omega.numel() else max(r, 1)
     _check(ctx.handle, lib().rp_project(ctx.handle, ctypes.byref(d), r, OMEGA_TYPES[omega_type],
-                                        seed, stream_id, _ptr(omega), ldo, ALGOS[algo], _ptr(y),
-                                        ldy, _stream()))
+                                        seed, stream_id, _ptr(omega), ldo, _ptr(col_scale), ALGOS[algo],
+                                        int(a_scale_exp), _ptr(y), ldy, _stream()))
     return y
 
 
@@ -199,7 +206,7 @@ def rp_omega_packed_size(n, r, algo="split_f16"):
 
 
 def rp_omega_pack(n, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo="split_f16",
-                  out=None, ctx=None):
+                  out=None, col_scale=None, ctx=None):
     """Omega in the kernels' fragment order (a uint8 device buffer)."""
     import torch
     ctx = ctx or default_context()
@@ -207,13 +214,13 @@ def rp_omega_pack(n, r, seed=0, stream_id=0, omega=None, omega_type="f16", algo=
         out = torch.empty(rp_omega_packed_size(n, r, algo), dtype=torch.uint8,
                           device=f"cuda:{ctx.device}")
     ldo = omega.stride(0) if omega is not None and omega.numel() else max(r, 1)
-    _check(ctx.handle, lib().rp_omega_pack(ctx.handle, seed, stream_id, _ptr(omega), ldo,
+    _check(ctx.handle, lib().rp_omega_pack(ctx.handle, seed, stream_id, _ptr(omega), ldo, _ptr(col_scale),
                                            OMEGA_TYPES[omega_type], n, r, ALGOS[algo], _ptr(out),
                                            _stream()))
     return out
 
 
-def rp_project_packed(a, r, packed, algo="split_f16", y=None, desc=None, ctx=None):
+def rp_project_packed(a, r, packed, algo="split_f16", y=None, desc=None, a_scale_exp=0, ctx=None):
     """Y = A Omega with Omega from rp_omega_pack (one kernel launch)."""
     import torch
     ctx = ctx or default_context()
@@ -222,7 +229,7 @@ def rp_project_packed(a, r, packed, algo="split_f16", y=None, desc=None, ctx=Non
         y = torch.empty((d.rows, r), dtype=torch.float32, device=f"cuda:{ctx.device}")
     ldy = y.stride(0) if y.numel() else max(r, 1)
     _check(ctx.handle, lib().rp_project_packed(ctx.handle, ctypes.byref(d), r, _ptr(packed),
-                                               ALGOS[algo], _ptr(y), ldy, _stream()))
+                                               ALGOS[algo], int(a_scale_exp), _ptr(y), ldy, _stream()))
     return y
 
 
@@ -237,8 +244,20 @@ def rp_split_f16(x, ctx=None):
     return hi, lo
 
 
-def rsvd(a, k, oversample=10, power_iters=0, seed=0, omega_type="f16", algo="split_f16", ctx=None):
+def rsvd_workspace_size(m, n, k, oversample=10, power_iters=0, omega_type="f16", algo="split_f16", ctx=None):
+    """Bytes of caller workspace rsvd() needs for these arguments."""
+    ctx = ctx or default_context()
+    out = ctypes.c_size_t(0)
+    _check(ctx.handle, lib().rsvd_workspace_size(ctx.handle, m, n, k, oversample, power_iters,
+                                                 OMEGA_TYPES[omega_type], ALGOS[algo], ctypes.byref(out)))
+    return out.value
+
+
+def rsvd(a, k, oversample=10, power_iters=0, seed=0, omega_type="f16", algo="split_f16", a_scale_exp=0,
+         work=None, outputs=None, ctx=None):
     """Randomized SVD (Algorithm 1) of the float32 CUDA matrix ``a`` (m x n).
+    ``work``: optional caller workspace (a CUDA tensor of at least
+    rsvd_workspace_size() bytes); None uses the context workspace.
     Returns (U m x k float32, S k float64, VT k x n float32)."""
     import torch
     ctx = ctx or default_context()
@@ -246,12 +265,16 @@ def rsvd(a, k, oversample=10, power_iters=0, seed=0, omega_type="f16", algo="spl
         raise TypeError("a must be a 2-D float32 CUDA tensor with unit column stride")
     m, n = a.shape
     dev = f"cuda:{ctx.device}"
-    u = torch.empty((m, k), dtype=torch.float32, device=dev)
-    sv = torch.empty((k,), dtype=torch.float64, device=dev)
-    vt = torch.empty((k, n), dtype=torch.float32, device=dev)
+    if outputs is not None:
+        u, sv, vt = outputs
+    else:
+        u = torch.empty((m, k), dtype=torch.float32, device=dev)
+        sv = torch.empty((k,), dtype=torch.float64, device=dev)
+        vt = torch.empty((k, n), dtype=torch.float32, device=dev)
+    wbytes = work.numel() * work.element_size() if work is not None else 0
     _check(ctx.handle, lib().rsvd(ctx.handle, m, n, _ptr(a), a.stride(0), k, oversample, power_iters, seed,
-                                  OMEGA_TYPES[omega_type], ALGOS[algo], _ptr(u), u.stride(0), _ptr(sv),
-                                  _ptr(vt), vt.stride(0), _stream()))
+                                  OMEGA_TYPES[omega_type], ALGOS[algo], int(a_scale_exp), _ptr(u), u.stride(0),
+                                  _ptr(sv), _ptr(vt), vt.stride(0), _ptr(work), wbytes, _stream()))
     return u, sv, vt
 
 
@@ -292,18 +315,20 @@ def rp_omega_generate_e4m3(n, r, seed=0, stream_id=0, ctx=None):
 
 def rp_project_grouped(problems, omega_type="f16", ctx=None):
     """Grouped split-FP16 projections.  ``problems``: list of (a, r, seed,
-    stream_id) with ``a`` a 2-D float32 CUDA tensor (unit column stride).
-    Returns the list of Y (float32, rows(a) x r)."""
+    stream_id[, a_scale_exp]) with ``a`` a 2-D float32 CUDA tensor (unit
+    column stride).  Returns the list of Y (float32, rows(a) x r)."""
     import torch
     ctx = ctx or default_context()
     n = len(problems)
     arr = (rp_project_problem * max(n, 1))()
     ys = []
-    for i, (a, r, seed, sid) in enumerate(problems):
+    for i, prob in enumerate(problems):
+        a, r, seed, sid = prob[:4]
         y = torch.empty((a.shape[0], r), dtype=torch.float32, device=f"cuda:{ctx.device}")
         ys.append(y)
         arr[i].A = desc_from_tensor(a)
         arr[i].r, arr[i].seed, arr[i].stream_id = r, seed, sid
+        arr[i].a_scale_exp = int(prob[4]) if len(prob) > 4 else 0
         arr[i].Y, arr[i].ldy = _ptr(y), max(r, 1)
     _check(ctx.handle, lib().rp_project_grouped(ctx.handle, n, arr, OMEGA_TYPES[omega_type], _stream()))
     return ys

@@ -70,7 +70,7 @@ def build(verbose=False):
                 print(out)
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
-         + ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas", "-lquadmath"])
+         + ["-lquadmath"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -44,8 +44,9 @@ extern "C" int rpmi_build_f16_thresholds(uint64_t* table, int capacity) {
     return -1;  // capacity too small
 }
 
-// Guide table over the top 12 bits of u: guide[b] = #{ t : T_t < b * 2^51 },
-// b = 0..4096, so that the pattern for u in bucket b lies in
+// Guide table over the top L = buckets_log2 bits of the 63-bit u (the
+// library uses L = 16): guide[b] = #{ t : T_t < b * 2^(63-L) }, b = 0..2^L,
+// so that the pattern for u in bucket b lies in
 // [guide[b], guide[b+1]] and only that slice of the table is searched.
 extern "C" void rpmi_build_guide(const uint64_t* table, int count, uint32_t* guide, int buckets_log2) {
     const int nb = 1 << buckets_log2;

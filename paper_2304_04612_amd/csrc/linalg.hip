@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_kernel(int64_t N, int64_t P, 
     typedef float f4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t i0 = (blockIdx.x * 4 + wave) * 64, j0 = blockIdx.y * (int64_t)64;
+    const int64_t i0 = (blockIdx.y * 4 + wave) * 64, j0 = blockIdx.x * (int64_t)64;
     const int64_t ia = i0 + 4 * c, jq = j0 + 4 * c;       // this lane's 4 rows of C (tiles 0..3), 4 columns
     const bool a_full = ia + 3 < N, q_full = jq + 3 < P;
     f4 acc[4][4];
@@ -363,6 +363,10 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     if (threadIdx.x == 0) P.flags[1 + (sweep & 1)] = 1;
 }
 
+__global__ void set_jacobi_prob_kernel(JacobiProb* dst, JacobiProb v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
 __global__ void jacobi_sweep_end_kernel(const JacobiProb* tab, int count, int sweep) {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) {
         int* f = tab[g].flags;
@@ -425,11 +429,6 @@ __global__ void svd_gather_kernel(const double* W, const double* Vin, int n, con
     }
 }
 
-__global__ void convert_f64_f32_kernel(const double* x, float* y, int64_t count) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = (float)x[i];
-}
-
 int grid1d(int64_t total, int block = 256) {
     int64_t g = (total + block - 1) / block;
     return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
@@ -450,13 +449,21 @@ hipError_t gemm_acc64_batched(int64_t M, int64_t N, int64_t K, double alpha, con
                               int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
                               int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const int64_t gx = (N + GT - 1) / GT, gm = (M + GT - 1) / GT;
+    if (gx > 0x7FFFFFFF) return hipErrorInvalidValue;
+    // row tiles on grid.y and problems on grid.z, each in chunks of at most 65535
     for (int64_t z0 = 0; z0 < batch; z0 += 65535) {
         const int64_t nb = batch - z0 < 65535 ? batch - z0 : 65535;
-        dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)nb);
-        hipLaunchKernelGGL((gemm_acc64_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M, N, K, alpha, a + z0 * sab, sam,
-                           sak, b + z0 * sbb, sbk, sbn, beta, c + z0 * scb, scm, scn, sab, sbb, scb);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int64_t y0 = 0; y0 < gm; y0 += 65535) {
+            const int64_t ny = gm - y0 < 65535 ? gm - y0 : 65535;
+            const int64_t r0 = y0 * GT;
+            dim3 grid((unsigned)gx, (unsigned)ny, (unsigned)nb);
+            hipLaunchKernelGGL((gemm_acc64_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M - r0, N, K, alpha,
+                               a + z0 * sab + r0 * sam, sam, sak, b + z0 * sbb, sbk, sbn, beta,
+                               c + z0 * scb + r0 * scm, scm, scn, sab, sbb, scb);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -582,11 +589,19 @@ hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t 
                     ((uintptr_t)Q & 15) == 0 && ((uintptr_t)C & 15) == 0;
     if (!ok)   // off the 16-byte path: the FP64-accumulating GEMM
         return gemm_acc64<float, float, float>(N, P, K, 1.0, A, 1, lda, Q, ldq, 1, 0.0, C, ldc, 1, s);
-    const int64_t gx = (N + 255) / 256, gy = (P + 63) / 64;
-    if (gx > 0x7FFFFFFF || gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_tn_f32_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, N, P, K, A, lda, Q, ldq,
-                       C, ldc);
-    return hipGetLastError();
+    // column tiles of C on grid.x (up to 2^31 - 1), 256-row blocks on grid.y in
+    // chunks of at most 65535
+    const int64_t gx = (P + 63) / 64, gy = (N + 255) / 256;
+    if (gx > 0x7FFFFFFF) return hipErrorInvalidValue;
+    for (int64_t y0 = 0; y0 < gy; y0 += 65535) {
+        const int64_t ny = gy - y0 < 65535 ? gy - y0 : 65535;
+        const int64_t r0 = y0 * 256;
+        hipLaunchKernelGGL(gemm_tn_f32_kernel, dim3((unsigned)gx, (unsigned)ny), dim3(256), 0, s, N - r0, P, K,
+                           A + r0, lda, Q, ldq, C + r0 * ldc, ldc);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
@@ -611,6 +626,11 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
     return hipGetLastError();
 }
 
+hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStream_t s) {
+    hipLaunchKernelGGL(set_jacobi_prob_kernel, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
+
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s) {
     hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(1024), 0, s, W, n, sig, order);
@@ -618,12 +638,6 @@ hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(svd_gather_kernel, dim3(grid1d((int64_t)n * ncols)), dim3(256), 0, s, W, V, n, sig, order,
                        ncols, Ur, Vr);
-    return hipGetLastError();
-}
-
-hipError_t convert_f64_f32(const double* x, float* y, int64_t count, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(convert_f64_f32_kernel, dim3(grid1d(count)), dim3(256), 0, s, x, y, count);
     return hipGetLastError();
 }
 

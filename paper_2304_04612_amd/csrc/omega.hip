@@ -38,7 +38,7 @@ __device__ __forceinline__ Words philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 }
 
 // k = #{ t : T_t <= u }: the guide table brackets k to one bucket of the
-// top 12 bits of u, then a binary search inside the bucket.
+// top kGuideLog2 (16) bits of u, then a binary search inside the bucket.
 __device__ __forceinline__ uint32_t f16_cell(uint64_t u, const uint64_t* __restrict__ T,
                                              const uint32_t* __restrict__ guide) {
     const uint32_t b = (uint32_t)(u >> (63 - kGuideLog2));
@@ -143,13 +143,36 @@ __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
     return (float)__builtin_bit_cast(_Float16, b);
 }
 
-// Reorder a row-major Omega (FP16 bits or FP32) into fragment order (FP16 or
-// FP32 fragments).  FP16 -> FP32 widening is exact; FP32 -> FP16 is not
-// offered.  One thread per (fragment, lane).
-template <bool SRC_F32, bool DST_F32>
-__global__ void pack_omega_kernel(const void* src, int64_t n, int64_t r, int64_t ldo, void* dst,
-                                  int64_t kb_count, int64_t nt_count) {
+// Value of an e4m3fn code (OCP E4M3FN: bias 7, no infinities, S.1111.111 is
+// NaN), exact in FP64.
+__device__ __forceinline__ double e4m3_decode(uint32_t code) {
+    const uint32_t e = (code >> 3) & 15u, m = code & 7u;
+    double v;
+    if (e == 15u && m == 7u) v = __builtin_nan("");
+    else if (e == 0u) v = (double)m * 0x1p-9;
+    else v = ldexp((double)(8u + m), (int)e - 10);
+    return (code & 0x80u) ? -v : v;
+}
+
+// A power-of-two column scale inside [2^-7, 2^15], the range in which
+// Omega8 / s is exact in FP16 for every e4m3 value.
+__device__ __forceinline__ bool scale_ok(float sc) {
+    int ex;
+    const float f = frexpf(sc, &ex);
+    return f == 0.5f && ex >= -6 && ex <= 16;
+}
+
+// Reorder a row-major Omega (FP16 bits, FP32, or e4m3 codes with column
+// scales) into fragment order (FP16 or FP32 fragments).  Widening to FP32 and
+// e4m3 / s_j into FP16 are exact; FP32 -> FP16 is not offered.  One thread per
+// (fragment, lane).  FP16 fragments meant for the split kernels are checked:
+// those kernels take the hi product against 2^11 Omega, exact below 32.
+template <OmegaSrc SRC, bool DST_F32>
+__global__ void pack_omega_kernel(const void* src, const float* col_scale, int64_t n, int64_t r, int64_t ldo,
+                                  void* dst, int64_t kb_count, int64_t nt_count, unsigned int* flag,
+                                  unsigned int flag_bit, unsigned int* status) {
     const int64_t total = kb_count * nt_count * 64;
+    bool bad = false, bad_scale = false;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int lane = (int)(q & 63), g = lane >> 4, c = lane & 15;
@@ -158,16 +181,27 @@ __global__ void pack_omega_kernel(const void* src, int64_t n, int64_t r, int64_t
         const int64_t col = nt * kNTile + c;
         float fv[8];
         uint16_t hv[8];
+        float sc = 1.0f;
+        if (SRC == OmegaSrc::E4M3 && col < r) {
+            sc = col_scale[col];
+            bad_scale |= !scale_ok(sc);
+        }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t row = kb * kKBlock + frag_slot(g, e);
             const bool in = row < n && col < r;
-            if (SRC_F32) {
+            if (SRC == OmegaSrc::F32) {
                 fv[e] = in ? static_cast<const float*>(src)[row * ldo + col] : 0.0f;
-            } else {
+                hv[e] = 0;
+            } else if (SRC == OmegaSrc::F16) {
                 hv[e] = in ? static_cast<const uint16_t*>(src)[row * ldo + col] : (uint16_t)0;
                 fv[e] = half_bits_to_float(hv[e]);
+            } else {
+                const uint32_t code = in ? static_cast<const uint8_t*>(src)[row * ldo + col] : 0u;
+                fv[e] = (float)(e4m3_decode(code) / (double)sc);      // exact for a valid scale
+                hv[e] = __builtin_bit_cast(uint16_t, (_Float16)fv[e]);
             }
+            if (!DST_F32) bad |= (hv[e] & 0x7FFFu) >= 0x5000u;       // |v| >= 32, inf or NaN
         }
         if (DST_F32) {
             float4* d = reinterpret_cast<float4*>(static_cast<float*>(dst) + q * 8);
@@ -182,6 +216,8 @@ __global__ void pack_omega_kernel(const void* src, int64_t n, int64_t r, int64_t
             *reinterpret_cast<uint4*>(static_cast<uint16_t*>(dst) + q * 8) = packed;
         }
     }
+    if (flag && bad) atomicOr(flag, flag_bit);
+    if (status && bad_scale) atomicOr(status, kStatusOmegaRange);
 }
 
 int grid_for(int64_t total, int block) {
@@ -303,21 +339,22 @@ hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
-                             const PackedOmega& dst, bool dst_f32, hipStream_t s) {
+hipError_t launch_pack_omega(const void* src, OmegaSrc type, const float* col_scale, int64_t n, int64_t r,
+                             int64_t ldo, const PackedOmega& dst, bool dst_f32, unsigned int* flag,
+                             unsigned int flag_bit, unsigned int* status, hipStream_t s) {
     const int64_t total = dst.kb_count * dst.nt_count * 64;
     if (total == 0) return hipSuccess;
     const int block = 256, grid = grid_for(total, block);
-    if (src_f32 && !dst_f32) return hipErrorInvalidValue;
-    if (src_f32)
-        hipLaunchKernelGGL((pack_omega_kernel<true, true>), dim3(grid), dim3(block), 0, s, src, n,
-                           r, ldo, dst.data, dst.kb_count, dst.nt_count);
-    else if (dst_f32)
-        hipLaunchKernelGGL((pack_omega_kernel<false, true>), dim3(grid), dim3(block), 0, s, src, n,
-                           r, ldo, dst.data, dst.kb_count, dst.nt_count);
-    else
-        hipLaunchKernelGGL((pack_omega_kernel<false, false>), dim3(grid), dim3(block), 0, s, src,
-                           n, r, ldo, dst.data, dst.kb_count, dst.nt_count);
+    if (type == OmegaSrc::F32 && !dst_f32) return hipErrorInvalidValue;
+#define RPMI_PACK(SRC, D32)                                                                                    \
+    hipLaunchKernelGGL((pack_omega_kernel<SRC, D32>), dim3(grid), dim3(block), 0, s, src, col_scale, n, r, ldo, \
+                       dst.data, dst.kb_count, dst.nt_count, flag, flag_bit, status)
+    if (type == OmegaSrc::F32) RPMI_PACK(OmegaSrc::F32, true);
+    else if (type == OmegaSrc::F16 && dst_f32) RPMI_PACK(OmegaSrc::F16, true);
+    else if (type == OmegaSrc::F16) RPMI_PACK(OmegaSrc::F16, false);
+    else if (dst_f32) RPMI_PACK(OmegaSrc::E4M3, true);
+    else RPMI_PACK(OmegaSrc::E4M3, false);
+#undef RPMI_PACK
     return hipGetLastError();
 }
 

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
                     half8 hi[T::TM], lo[T::TM];
 #pragma unroll
                     for (int tm = 0; tm < T::TM; ++tm)
-                        split8(ring[s][tm][kb][0], ring[s][tm][kb][1], hi[tm], lo[tm]);
+                        split8(ring[s][tm][kb][0] * p.a_scale, ring[s][tm][kb][1] * p.a_scale, hi[tm], lo[tm]);
 #pragma unroll
                     for (int j = 0; j < T::TN; ++j) {
                         const half8 b = lds[buf][(kb * T::NTB + wn * T::TN + j) * 64 + lane];
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
 
     if (any_nonfinite(acc_lo)) atomicOr(p.status, kStatusRange);
 
-    // epilogue: Y = acc_hi + 2^-11 acc_lo; lane (g, c) holds rows 4g..4g+3 of column c
+    // epilogue: Y = (acc_hi + 2^-11 acc_lo) 2^-s; lane (g, c) holds rows 4g..4g+3 of column c
 #pragma unroll
     for (int tm = 0; tm < T::TM; ++tm)
 #pragma unroll
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
             for (int e = 0; e < 4; ++e) {
                 const int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + 4 * g + e;
                 if (row < p.m && col < p.r)
-                    p.Y[row * p.ldy + col] = acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f;
+                    p.Y[row * p.ldy + col] = (acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f) * p.y_scale;
             }
         }
 }
@@ -234,6 +234,11 @@ __global__ void split_dump_kernel(const float* x, int64_t count, uint16_t* hi, u
     }
 }
 
+__global__ void fill_u32_kernel(unsigned int* p, int64_t count, unsigned int v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 __global__ void fill_f32_kernel(float* y, int64_t rows, int64_t cols, int64_t ld, float v) {
     const int64_t total = rows * cols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -252,7 +257,7 @@ bool vector_ok(const ProjArgs& a) {
 
 }  // namespace
 
-bool split_vector_ok(const ProjArgs& a) { return vector_ok(a); }
+bool split_fast_ok(const ProjArgs& a) { return vector_ok(a) && !a.two_acc && a.a_scale == 1.0f; }
 
 namespace {
 
@@ -317,7 +322,9 @@ hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, 
 template <class C, class TS>
 hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
     using TD = typename C::Tile;
-    if (vector_ok(a)) {
+    // the deep-pipeline kernel keeps one accumulator against 2^11 Omega and
+    // takes A unscaled; other requests go to the general kernel
+    if (split_fast_ok(a)) {
         GroupEntry e;
         e.p = a;
         e.tiles_m = (a.m + TD::BM - 1) / TD::BM;
@@ -350,6 +357,12 @@ hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16
                              hipStream_t s) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(split_dump_kernel, dim3(small_grid(count)), dim3(256), 0, s, x, count, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t count, unsigned int v, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(small_grid(count)), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
 }
 

@@ -13,14 +13,13 @@
 #include "../../include/rpmi.h"
 #include "rpmi_internal.h"
 
-#include <rocblas/rocblas.h>
-
 struct rp_ctx_s {
     int device = 0;
     uint64_t* d_thresholds = nullptr;
     uint32_t* d_guide = nullptr;
     int table_count = 0;
     unsigned int* d_status = nullptr;
+    unsigned int* d_scan = nullptr;      // result of scanning a caller Omega (read back by rp_project)
     void* ws = nullptr;
     size_t ws_bytes = 0;
     // contraction-split workspace of the split-FP16 projection: per-tile
@@ -44,7 +43,6 @@ struct rp_ctx_s {
     rpmi::JacobiProb* graph_jtab = nullptr;   // the batched Jacobi table read by the graph
     size_t graph_jtab_entries = 0;
     std::unordered_map<uint64_t, double> tuned_scale;
-    rocblas_handle blas = nullptr;         // plain FP32 GEMMs of rsvd (created on first use)
 };
 
 namespace {
@@ -126,6 +124,7 @@ const char* rp_status_string(rp_status s) {
         case RP_ERR_NOT_CONVERGED: return "RP_ERR_NOT_CONVERGED";
         case RP_ERR_NOMEM: return "RP_ERR_NOMEM";
         case RP_ERR_HIP: return "RP_ERR_HIP";
+        case RP_ERR_OMEGA_RANGE: return "RP_ERR_OMEGA_RANGE";
     }
     return "unknown rp_status";
 }
@@ -167,6 +166,7 @@ rp_status rp_create(rp_ctx* out, int device) {
     if ((e = hipMalloc(&ctx->d_thresholds, n * sizeof(uint64_t))) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->d_guide, guide.size() * sizeof(uint32_t))) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMalloc(&ctx->d_status, sizeof(unsigned int))) != hipSuccess) return cleanup(e, "hipMalloc");
+    if ((e = hipMalloc(&ctx->d_scan, sizeof(unsigned int))) != hipSuccess) return cleanup(e, "hipMalloc");
     if ((e = hipMemcpy(ctx->d_thresholds, thr.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(e, "hipMemcpy");
     if ((e = hipMemcpy(ctx->d_guide, guide.data(), guide.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
@@ -185,6 +185,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->d_thresholds) (void)hipFree(ctx->d_thresholds);
     if (ctx->d_guide) (void)hipFree(ctx->d_guide);
     if (ctx->d_status) (void)hipFree(ctx->d_status);
+    if (ctx->d_scan) (void)hipFree(ctx->d_scan);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->split_ws) (void)hipFree(ctx->split_ws);
     if (ctx->split_counters) (void)hipFree(ctx->split_counters);
@@ -193,7 +194,6 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
     if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->blas) (void)rocblas_destroy_handle(ctx->blas);
     delete ctx;
     return RP_OK;
 }
@@ -302,12 +302,24 @@ size_t raw_bytes(rp_omega_t type, rp_algo_t algo, int64_t n, int64_t r) {
 
 // Fill `pk` (fragment order for `algo`) from a caller Omega or from the
 // generator; `scratch` holds a row-major FP32/FP16 Omega when one has to be
-// generated before widening (FP32 algorithm without a caller Omega).
+// generated before widening (FP32 algorithm without a caller Omega).  A
+// caller Omega packed for the split algorithm is checked for entries outside
+// the single-accumulator range: `flag_bit` is set in *flag if one is found.
 rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void* omega, int64_t ldo,
-                      rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
-                      const rpmi::PackedOmega& pk, void* scratch, hipStream_t s) {
+                      const float* col_scale, rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
+                      const rpmi::PackedOmega& pk, void* scratch, hipStream_t s, unsigned int* flag = nullptr,
+                      unsigned int flag_bit = 0) {
+    const bool dst_f32 = algo == RP_ALGO_F32;
+    if (omega) {
+        const rpmi::OmegaSrc src = type == RP_OMEGA_F32 ? rpmi::OmegaSrc::F32
+                                 : type == RP_OMEGA_F16 ? rpmi::OmegaSrc::F16 : rpmi::OmegaSrc::E4M3;
+        if (src == rpmi::OmegaSrc::E4M3 && !col_scale)
+            return fail(ctx, RP_ERR_INVALID_ARG, "a caller e4m3 Omega needs its col_scale");
+        RP_HIP(ctx, rpmi::launch_pack_omega(omega, src, col_scale, n, r, ldo, pk, dst_f32, dst_f32 ? nullptr : flag,
+                                            flag_bit, ctx->d_status, s));
+        return RP_OK;
+    }
     if (type == RP_OMEGA_E4M3) {
-        if (omega) return fail(ctx, RP_ERR_UNSUPPORTED, "a caller e4m3 Omega is not supported (no column scales)");
         // FP32 Omega, column maxima, then the exact FP16 values Omega8 / s_j
         char* b = static_cast<char*>(scratch);
         float* w32 = reinterpret_cast<float*>(b);
@@ -315,22 +327,18 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
         unsigned int* cmax = reinterpret_cast<unsigned int*>(b + (((size_t)n * r * 6 + 255) & ~size_t(255)));
         RP_HIP(ctx, rpmi::launch_omega_e4m3(tables(ctx), seed, stream_id, n, r, w32, cmax, nullptr, 0, f16, r, nullptr,
                                             s));
-        RP_HIP(ctx, rpmi::launch_pack_omega(f16, false, n, r, r, pk, algo == RP_ALGO_F32, s));
+        RP_HIP(ctx, rpmi::launch_pack_omega(f16, rpmi::OmegaSrc::F16, nullptr, n, r, r, pk, dst_f32, nullptr, 0, nullptr,
+                                            s));
         return RP_OK;
     }
     if (algo == RP_ALGO_SPLIT_F16) {
-        if (omega) RP_HIP(ctx, rpmi::launch_pack_omega(omega, false, n, r, ldo, pk, false, s));
-        else RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), seed, stream_id, n, r, pk, s));
+        RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), seed, stream_id, n, r, pk, s));
         return RP_OK;
     }
     const bool src_f32 = type == RP_OMEGA_F32;
-    const void* src = omega;
-    if (!omega) {
-        RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, src_f32, scratch, r, s));
-        src = scratch;
-        ldo = r;
-    }
-    RP_HIP(ctx, rpmi::launch_pack_omega(src, src_f32, n, r, ldo, pk, true, s));
+    RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, src_f32, scratch, r, s));
+    RP_HIP(ctx, rpmi::launch_pack_omega(scratch, src_f32 ? rpmi::OmegaSrc::F32 : rpmi::OmegaSrc::F16, nullptr, n, r, r,
+                                        pk, true, nullptr, 0, nullptr, s));
     return RP_OK;
 }
 
@@ -366,25 +374,58 @@ rp_status ensure_split_workspace(rp_ctx ctx, size_t counters, size_t partials) {
     return RP_OK;
 }
 
-rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi::PackedOmega& pk,
-                            rp_algo_t algo, float* Y, int64_t ldy, hipStream_t s) {
+// Split-K buffers supplied by a caller workspace instead of the context's.
+struct SplitBuffers {
+    unsigned int* counters;           // zero on entry, left zero
+    float* partial;
+    size_t counter_bytes, partial_bytes;
+};
+
+rpmi::ProjArgs proj_args(rp_ctx ctx, const rp_desc* A, int64_t r, const void* omega, int64_t nt_count, float* Y,
+                         int64_t ldy, int32_t a_scale_exp) {
     rpmi::ProjArgs a;
     a.A = A->ptr; a.m = A->rows; a.n = A->cols;
     a.s_row = A->s_row;
     a.k_inner = A->k_inner;
     a.s_k_outer = A->s_k_outer;
-    a.omega = pk.data; a.nt_count = pk.nt_count;
+    a.omega = omega; a.nt_count = nt_count;
     a.Y = Y; a.ldy = ldy; a.r = r;
     a.status = ctx->d_status;
-    a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+    a.a_scale = ldexpf(1.0f, a_scale_exp);
+    a.y_scale = ldexpf(1.0f, -a_scale_exp);
+    return a;
+}
+
+bool scale_exp_ok(rp_ctx ctx, int32_t s, rp_status* st) {
+    if (s < -64 || s > 64) {
+        *st = fail(ctx, RP_ERR_INVALID_ARG, "a_scale_exp %d outside [-64, 64]", (int)s);
+        return false;
+    }
+    return true;
+}
+
+rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi::PackedOmega& pk,
+                            rp_algo_t algo, float* Y, int64_t ldy, hipStream_t s, int32_t a_scale_exp = 0,
+                            bool two_acc = false, const SplitBuffers* sb = nullptr) {
+    rpmi::ProjArgs a = proj_args(ctx, A, r, pk.data, pk.nt_count, Y, ldy, a_scale_exp);
+    a.two_acc = two_acc;
     if (algo == RP_ALGO_SPLIT_F16) {
-        const rpmi::SplitPlan plan = rpmi::plan_split_f16(a.m, a.n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
-        if (plan.ksplit > 1) {
-            rp_status st = ensure_split_workspace(ctx, plan.counter_bytes, plan.partial_bytes);
-            if (st != RP_OK) return st;
-            a.ksplit = plan.ksplit;
-            a.counters = ctx->split_counters;
-            a.partial = static_cast<float*>(ctx->split_ws);
+        if (rpmi::split_fast_ok(a)) {
+            const rpmi::SplitPlan plan = rpmi::plan_split_f16(a.m, a.n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
+            if (plan.ksplit > 1) {
+                if (sb) {
+                    if (plan.counter_bytes > sb->counter_bytes || plan.partial_bytes > sb->partial_bytes)
+                        return fail(ctx, RP_ERR_INVALID_ARG, "workspace too small for the contraction split");
+                    a.counters = sb->counters;
+                    a.partial = sb->partial;
+                } else {
+                    rp_status st = ensure_split_workspace(ctx, plan.counter_bytes, plan.partial_bytes);
+                    if (st != RP_OK) return st;
+                    a.counters = ctx->split_counters;
+                    a.partial = static_cast<float*>(ctx->split_ws);
+                }
+                a.ksplit = plan.ksplit;
+            }
         }
         RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
     } else {
@@ -412,7 +453,7 @@ rp_status ensure_table(rp_ctx ctx, size_t entries) {
 // compute units (in proportion to its A bytes, times `cu_scale`), the split-K
 // counters and partials are laid out in the context buffers, and the table
 // entries (narrow ones first) are returned with the block count of each
-// width.  Problems must be on the 16-byte path (split_vector_ok).
+// width.  Problems must be on the 16-byte path (split_fast_ok).
 struct GroupPlan {
     std::vector<rpmi::GroupEntry> entries;
     int narrow_count = 0;
@@ -493,14 +534,8 @@ rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const*
     std::vector<rpmi::ProjArgs> probs(count);
     for (int g = 0; g < count; ++g) {
         if (A[g]->rows == 0 || A[g]->cols == 0 || r[g] == 0) return RP_ERR_UNSUPPORTED;
-        rpmi::ProjArgs& a = probs[g];
-        a.A = A[g]->ptr; a.m = A[g]->rows; a.n = A[g]->cols;
-        a.s_row = A[g]->s_row; a.k_inner = A[g]->k_inner; a.s_k_outer = A[g]->s_k_outer;
-        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
-        a.Y = Y[g]; a.ldy = ldy[g]; a.r = r[g];
-        a.status = ctx->d_status;
-        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
-        if (!rpmi::split_vector_ok(a)) return RP_ERR_UNSUPPORTED;
+        probs[g] = proj_args(ctx, A[g], r[g], pk[g].data, pk[g].nt_count, Y[g], ldy[g], 0);
+        if (!rpmi::split_fast_ok(probs[g])) return RP_ERR_UNSUPPORTED;
     }
     GroupPlan gp;
     rp_status st = plan_group(ctx, probs, 1.0, &gp);
@@ -521,8 +556,8 @@ rp_status rp_omega_packed_size(int64_t n, int64_t r, rp_algo_t algo, size_t* byt
 }
 
 rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void* omega,
-                        int64_t ldo, rp_omega_t type, int64_t n, int64_t r, rp_algo_t algo,
-                        void* packed, void* stream) {
+                        int64_t ldo, const float* col_scale, rp_omega_t type, int64_t n, int64_t r,
+                        rp_algo_t algo, void* packed, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, type, algo, &st)) return st;
@@ -537,16 +572,18 @@ rp_status rp_omega_pack(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const voi
         if ((st = ensure_workspace(ctx, raw_bytes(type, algo, n, r))) != RP_OK) return st;
         scratch = ctx->ws;
     }
-    return fill_packed(ctx, seed, stream_id, omega, ldo, type, n, r, algo, pk, scratch, (hipStream_t)stream);
+    return fill_packed(ctx, seed, stream_id, omega, ldo, col_scale, type, n, r, algo, pk, scratch,
+                       (hipStream_t)stream, ctx->d_status, rpmi::kStatusOmegaRange);
 }
 
 rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
-                            rp_algo_t algo, float* Y, int64_t ldy, void* stream) {
+                            rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!desc_ok(ctx, A, &st)) return st;
     if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16)
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown algorithm %d", (int)algo);
+    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
     if (r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative r %lld", (long long)r);
     const int64_t m = A->rows, n = A->cols;
     if (m == 0 || r == 0) return RP_OK;
@@ -560,22 +597,26 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
     }
     if (!packed) return fail(ctx, RP_ERR_INVALID_ARG, "packed is NULL");
     if (!proj_layout_ok(ctx, A, &st)) return st;
-    return launch_projection(ctx, A, r, packed_geometry(n, r, algo, const_cast<void*>(packed)), algo, Y, ldy, s);
+    return launch_projection(ctx, A, r, packed_geometry(n, r, algo, const_cast<void*>(packed)), algo, Y, ldy, s,
+                             algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0);
 }
 
 rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_type, uint64_t seed,
-                     uint32_t stream_id, const void* omega, int64_t ldo, rp_algo_t algo, float* Y,
-                     int64_t ldy, void* stream) {
+                     uint32_t stream_id, const void* omega, int64_t ldo, const float* col_scale, rp_algo_t algo,
+                     int32_t a_scale_exp, float* Y, int64_t ldy, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!desc_ok(ctx, A, &st)) return st;
     if (r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative r %lld", (long long)r);
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
     const int64_t m = A->rows, n = A->cols;
     if (m == 0 || r == 0) return RP_OK;
     if (!Y) return fail(ctx, RP_ERR_INVALID_ARG, "Y is NULL");
     if (ldy < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldy %lld < r %lld", (long long)ldy, (long long)r);
     if (omega && ldo < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldo %lld < r %lld", (long long)ldo, (long long)r);
+    if (omega && omega_type == RP_OMEGA_E4M3 && !col_scale)
+        return fail(ctx, RP_ERR_INVALID_ARG, "a caller e4m3 Omega needs its col_scale");
     hipStream_t s = (hipStream_t)stream;
     RP_HIP(ctx, hipSetDevice(ctx->device));
     if (n == 0) {
@@ -590,9 +631,21 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
     if ((st = ensure_workspace(ctx, raw_off + rb)) != RP_OK) return st;
     pk.data = ctx->ws;
     void* raw = static_cast<char*>(ctx->ws) + raw_off;
-    if ((st = fill_packed(ctx, seed, stream_id, omega, ldo, omega_type, n, r, algo, pk, raw, s)) != RP_OK)
+    // a caller Omega for the split kernels is scanned; entries the single
+    // accumulator cannot take route the call to the two-accumulator kernel
+    const bool scan = omega && algo == RP_ALGO_SPLIT_F16;
+    if (scan) RP_HIP(ctx, rpmi::launch_fill_u32(ctx->d_scan, 1, 0u, s));
+    if ((st = fill_packed(ctx, seed, stream_id, omega, ldo, col_scale, omega_type, n, r, algo, pk, raw, s,
+                          scan ? ctx->d_scan : nullptr, 1u)) != RP_OK)
         return st;
-    return launch_projection(ctx, A, r, pk, algo, Y, ldy, s);
+    bool two_acc = false;
+    if (scan) {
+        unsigned int word = 0;
+        RP_HIP(ctx, hipMemcpyAsync(&word, ctx->d_scan, sizeof word, hipMemcpyDeviceToHost, s));
+        RP_HIP(ctx, hipStreamSynchronize(s));
+        two_acc = word != 0;
+    }
+    return launch_projection(ctx, A, r, pk, algo, Y, ldy, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, two_acc);
 }
 
 }  // extern "C"
@@ -713,47 +766,33 @@ rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) 
 
 // Algorithm 1 after Y = A Omega, up to the small SVD: the power scheme
 // (re-orthonormalised), then Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B with R_B^T
-// left in w.MW.  Launches kernels and device-to-device copies only
-// (capturable in a graph).
-// Z = A^T Q (n x p, row-major) for A (m x n, lda) and Q (m x p): with
-// `blas`, the library FP32 GEMM (column-major view: Z^T = Q^T A, p x n);
-// otherwise this library's FP32 MFMA kernel (capturable, no library state).
-rp_status gemm_at_q(rp_ctx ctx, bool blas, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda,
-                    const float* Q, float* Z, hipStream_t s) {
-    if (blas) {
-        if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success)
-            return fail(ctx, RP_ERR_HIP, "rocblas_create_handle failed");
-        if (rocblas_set_stream(ctx->blas, s) != rocblas_status_success)
-            return fail(ctx, RP_ERR_HIP, "rocblas_set_stream failed");
-        const float one = 1.0f, zero = 0.0f;
-        if (rocblas_sgemm(ctx->blas, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)p,
-                          (rocblas_int)n, (rocblas_int)m, &one, Q, (rocblas_int)p, A, (rocblas_int)lda, &zero, Z,
-                          (rocblas_int)p) != rocblas_status_success)
-            return fail(ctx, RP_ERR_HIP, "rocblas_sgemm failed");
-        return RP_OK;
-    }
+// left in w.MW.  Launches kernels only (capturable in a graph).
+// Z = A^T Q (n x p, row-major) for A (m x n, lda) and Q (m x p).
+rp_status gemm_at_q(rp_ctx ctx, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda, const float* Q,
+                    float* Z, hipStream_t s) {
     RP_HIP(ctx, rpmi::gemm_tn_f32(n, p, m, A, lda, Q, p, Z, p, s));
     return RP_OK;
 }
 
 rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p, int32_t power_iters,
-                          float* Y, const RsvdScratch& w, hipStream_t s, bool blas = false) {
+                          float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
     const int64_t m = q.m, n = q.n, lda = q.lda;
     const float* A = q.A;
     for (int32_t t = 0; t < power_iters; ++t) {
         if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Z = A^T Q (n x p)
-        if ((st = gemm_at_q(ctx, blas, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
+        if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
         if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Y = A W (FP32 x FP32): the FP32 projection kernel with W in fragment order
-        RP_HIP(ctx, rpmi::launch_pack_omega(w.W, true, n, p, p, w.pkw, true, s));
+        RP_HIP(ctx, rpmi::launch_pack_omega(w.W, rpmi::OmegaSrc::F32, nullptr, n, p, p, w.pkw, true, nullptr, 0, nullptr,
+                                            s));
         if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
     }
     // Algorithm 1 line 2: Q = QR(Y)
     if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
     // line 3: B^T = A^T Q (n x p)
-    if ((st = gemm_at_q(ctx, blas, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
+    if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
     // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
     return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, w.GP, s);
 }
@@ -769,21 +808,43 @@ rp_status rsvd_after_svd(rp_ctx ctx, const rp_rsvd_problem& q, int64_t p, const 
     return RP_OK;
 }
 
-#ifndef RPMI_RSVD_BLAS
-#define RPMI_RSVD_BLAS 1
-#endif
-// The whole of Algorithm 1 after the projection, for one problem (the
-// Jacobi table entry is written with a stream-ordered host copy; A^T Q by the
-// library FP32 GEMM).
+// The whole of Algorithm 1 after the projection, for one problem.
 rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& q, int64_t p,
                                 int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
-    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s, RPMI_RSVD_BLAS != 0)) != RP_OK) return st;
-    const rpmi::JacobiProb jp{w.MW, w.MV, (int)p, 0, w.jflags};
-    RP_HIP(ctx, hipMemcpyAsync(w.jtab, &jp, sizeof jp, hipMemcpyHostToDevice, s));
+    if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s)) != RP_OK) return st;
+    RP_HIP(ctx, rpmi::launch_set_jacobi_prob(w.jtab, rpmi::JacobiProb{w.MW, w.MV, (int)p, 0, w.jflags}, s));
     RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,
                                        ctx->d_status, s));
     return rsvd_after_svd(ctx, q, p, w, s);
+}
+
+// Workspace layout of one rsvd() call: packed Omega, generator scratch, Y,
+// the per-problem scratch and the split-K counters and partials of the
+// projection, all in one 256-byte aligned block.
+struct RsvdPlan {
+    rpmi::PackedOmega pk;
+    RsvdScratch w;
+    rpmi::SplitPlan sp;
+    size_t o_pk, o_raw, o_y, o_w, o_cnt, o_part, bytes;
+};
+
+RsvdPlan rsvd_plan(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64_t oversample, rp_omega_t omega_type,
+                   rp_algo_t algo) {
+    RsvdPlan pl;
+    const int64_t p = k + oversample;
+    Arena ar;
+    pl.pk = packed_geometry(n, p, algo, nullptr);
+    pl.o_pk = ar.take(packed_bytes(pl.pk, algo));
+    pl.o_raw = ar.take(raw_bytes(omega_type, algo, n, p));   // generator scratch
+    pl.o_y = ar.take((size_t)m * p * 4);
+    pl.o_w = pl.w.layout(ar, m, n, k, p);
+    pl.sp = algo == RP_ALGO_SPLIT_F16 ? rpmi::plan_split_f16(m, n, p, ctx->num_cus > 0 ? ctx->num_cus : 256)
+                                      : rpmi::SplitPlan{1, 0, 0};
+    pl.o_cnt = ar.take(pl.sp.counter_bytes);
+    pl.o_part = ar.take(pl.sp.partial_bytes);
+    pl.bytes = ar.used;
+    return pl;
 }
 
 uint64_t mix(uint64_t h, uint64_t v) {
@@ -795,33 +856,57 @@ uint64_t mix(uint64_t h, uint64_t v) {
 
 extern "C" {
 
+rp_status rsvd_workspace_size(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64_t oversample,
+                              int32_t power_iters, rp_omega_t omega_type, rp_algo_t algo, size_t* bytes) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    if (!bytes) return fail(ctx, RP_ERR_INVALID_ARG, "bytes is NULL");
+    rp_status st;
+    if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    const int64_t p = k + oversample;
+    if (m <= 0 || n <= 0 || k <= 0 || oversample < 0 || power_iters < 0 || p > m || p > n || p > 1024)
+        return fail(ctx, RP_ERR_INVALID_ARG, "invalid sizes (m %lld, n %lld, k %lld, s %lld, q %d)", (long long)m,
+                    (long long)n, (long long)k, (long long)oversample, (int)power_iters);
+    *bytes = rsvd_plan(ctx, m, n, k, oversample, omega_type, algo).bytes;
+    return RP_OK;
+}
+
 rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, int64_t k, int64_t oversample,
-               int32_t power_iters, uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* U, int64_t ldu,
-               double* S, float* VT, int64_t ldvt, void* stream) {
+               int32_t power_iters, uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, int32_t a_scale_exp,
+               float* U, int64_t ldu, double* S, float* VT, int64_t ldvt, void* work, size_t work_bytes,
+               void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
     const rp_rsvd_problem prob{m, n, A, lda, k, oversample, U, ldu, S, VT, ldvt};
     if ((st = rsvd_check(ctx, prob, power_iters)) != RP_OK) return st;
+    const RsvdPlan pl = rsvd_plan(ctx, m, n, k, oversample, omega_type, algo);
+    if (work) {
+        if (reinterpret_cast<uintptr_t>(work) & 255) return fail(ctx, RP_ERR_INVALID_ARG, "work is not 256-byte aligned");
+        if (work_bytes < pl.bytes)
+            return fail(ctx, RP_ERR_INVALID_ARG, "work_bytes %zu < %zu (rsvd_workspace_size)", work_bytes, pl.bytes);
+    }
     hipStream_t s = (hipStream_t)stream;
     RP_HIP(ctx, hipSetDevice(ctx->device));
     const int64_t p = k + oversample;
     const rp_desc dA{A, m, n, lda, n, 1, 0};
-    Arena ar;
-    rpmi::PackedOmega pk = packed_geometry(n, p, algo, nullptr);
-    const size_t o_pk = ar.take(packed_bytes(pk, algo));
-    const size_t o_raw = ar.take(raw_bytes(omega_type, algo, n, p));   // generator scratch
-    const size_t o_y = ar.take((size_t)m * p * 4);
-    RsvdScratch w;
-    const size_t o_w = w.layout(ar, m, n, k, p);
-    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
-    char* base = static_cast<char*>(ctx->ws);
-    pk.data = base + o_pk;
-    w.bind(base + o_w);
-    float* Y = reinterpret_cast<float*>(base + o_y);
+    if (!work && (st = ensure_workspace(ctx, pl.bytes)) != RP_OK) return st;
+    char* base = static_cast<char*>(work ? work : ctx->ws);
+    rpmi::PackedOmega pk = pl.pk;
+    pk.data = base + pl.o_pk;
+    RsvdScratch w = pl.w;
+    w.bind(base + pl.o_w);
+    float* Y = reinterpret_cast<float*>(base + pl.o_y);
+    SplitBuffers sb{reinterpret_cast<unsigned int*>(base + pl.o_cnt), reinterpret_cast<float*>(base + pl.o_part),
+                    pl.sp.counter_bytes, pl.sp.partial_bytes};
+    if (pl.sp.counter_bytes)
+        RP_HIP(ctx, rpmi::launch_fill_u32(sb.counters, (int64_t)(pl.sp.counter_bytes / 4), 0u, s));
     // Algorithm 1 line 1: Y = A Omega
-    if ((st = fill_packed(ctx, seed, 0, nullptr, 0, omega_type, n, p, algo, pk, base + o_raw, s)) != RP_OK) return st;
-    if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s)) != RP_OK) return st;
+    if ((st = fill_packed(ctx, seed, 0, nullptr, 0, nullptr, omega_type, n, p, algo, pk, base + pl.o_raw, s)) != RP_OK)
+        return st;
+    if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, false,
+                                &sb)) != RP_OK)
+        return st;
     return rsvd_after_projection(ctx, dA, prob, p, power_iters, Y, w, s);
 }
 
@@ -835,6 +920,7 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
     for (int32_t g = 0; g < count; ++g) {
         const rp_project_problem& q = probs[g];
         if (!desc_ok(ctx, &q.A, &st)) return st;
+        if (!scale_exp_ok(ctx, q.a_scale_exp, &st)) return st;
         if (q.r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "problem %d: negative r", (int)g);
         if (q.A.rows > 0 && q.r > 0) {
             if (!q.Y || q.ldy < q.r) return fail(ctx, RP_ERR_INVALID_ARG, "problem %d: bad Y", (int)g);
@@ -864,19 +950,14 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
             continue;
         }
         pk[g].data = static_cast<char*>(ctx->ws) + off[g];
-        if ((st = fill_packed(ctx, q.seed, q.stream_id, nullptr, 0, omega_type, q.A.cols, q.r, RP_ALGO_SPLIT_F16, pk[g],
-                              static_cast<char*>(ctx->ws) + o_raw, s)) != RP_OK)
+        if ((st = fill_packed(ctx, q.seed, q.stream_id, nullptr, 0, nullptr, omega_type, q.A.cols, q.r,
+                              RP_ALGO_SPLIT_F16, pk[g], static_cast<char*>(ctx->ws) + o_raw, s)) != RP_OK)
             return st;
-        rpmi::ProjArgs a;
-        a.A = q.A.ptr; a.m = q.A.rows; a.n = q.A.cols;
-        a.s_row = q.A.s_row; a.k_inner = q.A.k_inner; a.s_k_outer = q.A.s_k_outer;
-        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
-        a.Y = q.Y; a.ldy = q.ldy; a.r = q.r;
-        a.status = ctx->d_status;
-        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
-        if (rpmi::split_vector_ok(a)) {
+        const rpmi::ProjArgs a = proj_args(ctx, &q.A, q.r, pk[g].data, pk[g].nt_count, q.Y, q.ldy, q.a_scale_exp);
+        if (rpmi::split_fast_ok(a)) {
             grouped.push_back(a);
-        } else if ((st = launch_projection(ctx, &q.A, q.r, pk[g], RP_ALGO_SPLIT_F16, q.Y, q.ldy, s)) != RP_OK) {
+        } else if ((st = launch_projection(ctx, &q.A, q.r, pk[g], RP_ALGO_SPLIT_F16, q.Y, q.ldy, s,
+                                           q.a_scale_exp)) != RP_OK) {
             return st;
         }
     }
@@ -935,13 +1016,11 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     uint64_t sig = mix(0, (uint64_t)count);
     for (int32_t g = 0; g < count; ++g) {
         const rp_rsvd_problem& q = probs[g];
-        rpmi::ProjArgs a;
-        a.A = q.A; a.m = q.m; a.n = q.n; a.s_row = q.lda; a.k_inner = q.n; a.s_k_outer = 0;
-        a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
-        a.Y = reinterpret_cast<float*>(base + o_y[g]); a.ldy = q.k + q.oversample; a.r = q.k + q.oversample;
-        a.status = ctx->d_status;
-        a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
-        if (algo == RP_ALGO_SPLIT_F16 && rpmi::split_vector_ok(a)) grouped.push_back(a);
+        const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+        const int64_t p = q.k + q.oversample;
+        const rpmi::ProjArgs a = proj_args(ctx, &dA, p, pk[g].data, pk[g].nt_count,
+                                           reinterpret_cast<float*>(base + o_y[g]), p, 0);
+        if (algo == RP_ALGO_SPLIT_F16 && rpmi::split_fast_ok(a)) grouped.push_back(a);
         else single.push_back(g);
         sig = mix(mix(mix(sig, (uint64_t)q.m), (uint64_t)q.n), (uint64_t)a.r);
     }
@@ -968,8 +1047,8 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     auto gen_omega = [&](hipStream_t st_) -> rp_status {
         for (int32_t g = 0; g < count; ++g) {
             const rp_rsvd_problem& q = probs[g];
-            rp_status r2 = fill_packed(ctx, seed, (uint32_t)g, nullptr, 0, omega_type, q.n, q.k + q.oversample, algo,
-                                       pk[g], base + o_raw, st_);
+            rp_status r2 = fill_packed(ctx, seed, (uint32_t)g, nullptr, 0, nullptr, omega_type, q.n, q.k + q.oversample,
+                                       algo, pk[g], base + o_raw, st_);
             if (r2 != RP_OK) return r2;
         }
         return RP_OK;
@@ -1064,12 +1143,8 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
             const int64_t p = q.k + q.oversample;
             if (algo == RP_ALGO_SPLIT_F16) {
                 // off the 16-byte path: the general split kernel (no table)
-                rpmi::ProjArgs a;
-                a.A = q.A; a.m = q.m; a.n = q.n; a.s_row = q.lda; a.k_inner = q.n; a.s_k_outer = 0;
-                a.omega = pk[g].data; a.nt_count = pk[g].nt_count;
-                a.Y = reinterpret_cast<float*>(base + o_y[g]); a.ldy = p; a.r = p;
-                a.status = ctx->d_status;
-                a.ksplit = 1; a.partial = nullptr; a.counters = nullptr;
+                const rpmi::ProjArgs a = proj_args(ctx, &dA, p, pk[g].data, pk[g].nt_count,
+                                                   reinterpret_cast<float*>(base + o_y[g]), p, 0);
                 RP_HIP(ctx, rpmi::launch_project_split_f16(a, cs));
             } else if ((r2 = launch_projection(ctx, &dA, p, pk[g], algo, reinterpret_cast<float*>(base + o_y[g]), p,
                                                cs)) != RP_OK) {
@@ -1202,7 +1277,7 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
         ldw[i] = ranks[i];
         dp[i] = &desc[i];
         const int64_t cols = total / dims[i];
-        if ((st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, omega_type, cols, ranks[i], algo, pk[i],
+        if ((st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, pk[i],
                               base + o_raw, s)) != RP_OK)
             return st;
     }
@@ -1290,6 +1365,7 @@ rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* o
     RP_HIP(ctx, hipMemcpy(&word, ctx->d_status, sizeof word, hipMemcpyDeviceToHost));
     if (clear) RP_HIP(ctx, hipMemset(ctx->d_status, 0, sizeof(unsigned int)));
     *out = (word & rpmi::kStatusRange) ? RP_ERR_RANGE
+         : (word & rpmi::kStatusOmegaRange) ? RP_ERR_OMEGA_RANGE
          : (word & rpmi::kStatusNotSpd) ? RP_ERR_NOT_SPD
          : (word & rpmi::kStatusNotConverged) ? RP_ERR_NOT_CONVERGED
          : RP_OK;

@@ -38,20 +38,26 @@ struct PackedOmega {
 
 // ---------------------------------------------------------------- projection
 struct ProjArgs {
-    const float* A;
-    int64_t m, n;
-    int64_t s_row, k_inner, s_k_outer;
-    const void* omega;                // packed fragments (FP16 or FP32)
-    int64_t nt_count;                 // fragment tiles per 32-row block
-    float* Y;
-    int64_t ldy, r;
-    unsigned int* status;             // device status word
+    const float* A = nullptr;
+    int64_t m = 0, n = 0;
+    int64_t s_row = 0, k_inner = 1, s_k_outer = 0;
+    const void* omega = nullptr;      // packed fragments (FP16 or FP32)
+    int64_t nt_count = 0;             // fragment tiles per 32-row block
+    float* Y = nullptr;
+    int64_t ldy = 0, r = 0;
+    unsigned int* status = nullptr;   // device status word
     // contraction split (split-FP16 path): ksplit workgroups share one output
     // tile; each writes its partial sums to `partial`, the last one to finish
     // (per-tile counter) adds them in a fixed order and writes Y
-    int ksplit;
-    float* partial;                   // ksplit * tiles * BM * BN floats
-    unsigned int* counters;           // one per output tile, zero between launches
+    int ksplit = 1;
+    float* partial = nullptr;         // ksplit * tiles * BM * BN floats
+    unsigned int* counters = nullptr; // one per output tile, zero between launches
+    // caller pre-scale of A (split path): the split takes a_scale * A and the
+    // epilogue multiplies by y_scale; a_scale = 2^s, y_scale = 2^-s, both exact
+    float a_scale = 1.0f, y_scale = 1.0f;
+    // host-side routing: take the general kernel with two accumulators
+    // (eq:shgemm-3 as written), which has no bound on |Omega|
+    bool two_acc = false;
 };
 
 // Several split-FP16 projections in one launch (all on the 16-byte path and
@@ -73,7 +79,7 @@ hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t b
                                    hipStream_t s);
 hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
                                      hipStream_t s);
-bool split_vector_ok(const ProjArgs& a);
+bool split_fast_ok(const ProjArgs& a);
 
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
 // contraction split it will use; the counters must be zero initially.
@@ -87,6 +93,7 @@ SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus);
 constexpr unsigned int kStatusRange = 1u;
 constexpr unsigned int kStatusNotSpd = 2u;
 constexpr unsigned int kStatusNotConverged = 4u;
+constexpr unsigned int kStatusOmegaRange = 8u;
 
 // Column padding the packed Omega must provide for each algorithm: the
 // kernels read whole column blocks.
@@ -106,14 +113,23 @@ hipError_t launch_omega_e4m3(const OmegaTables& t, uint64_t seed, uint32_t strea
                              float* scale, hipStream_t s);
 hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
-hipError_t launch_pack_omega(const void* src, bool src_f32, int64_t n, int64_t r, int64_t ldo,
-                             const PackedOmega& dst, bool dst_f32, hipStream_t s);
+// Row-major Omega formats a caller can supply
+enum class OmegaSrc { F16, F32, E4M3 };
+// Reorder a caller (or generated) row-major Omega into fragment order.  For
+// FP16 fragments every value v is checked: |v| >= 32 or a non-finite value
+// sets `flag_bit` in *flag (when flag != NULL).  An e4m3 column scale outside
+// the powers of two in [2^-7, 2^15] sets kStatusOmegaRange in *status (when
+// status != NULL).
+hipError_t launch_pack_omega(const void* src, OmegaSrc type, const float* col_scale, int64_t n, int64_t r,
+                             int64_t ldo, const PackedOmega& dst, bool dst_f32, unsigned int* flag,
+                             unsigned int flag_bit, unsigned int* status, hipStream_t s);
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s);
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s);
 hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                              hipStream_t s);
 hipError_t launch_fill_f32(float* y, int64_t rows, int64_t cols, int64_t ld, float v,
                            hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int64_t count, unsigned int v, hipStream_t s);
 
 // ---------------------------------------------------------------- linalg.hip
 template <class TA, class TB, class TC>
@@ -151,11 +167,12 @@ struct JacobiProb {
     int pair_start;
     int* flags;
 };
+// Write one Jacobi table entry from the kernel arguments (no host copy).
+hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStream_t s);
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
                             double tol, unsigned int* status, hipStream_t s);
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
-hipError_t convert_f64_f32(const double* x, float* y, int64_t count, hipStream_t s);
 
 }  // namespace rpmi
 

@@ -49,8 +49,8 @@ def test_status_strings(L):
 def test_null_context_rejected_without_gpu(L):
     import paper_2304_04612_amd as rp
     d = rp.rp_desc(0, 4, 4, 4, 4, 1, 0)
-    st = L.rp_project(None, ctypes.byref(d), 4, rp.RP_OMEGA_F16, 0, 0, None, 4,
-                      rp.RP_ALGO_SPLIT_F16, None, 4, None)
+    st = L.rp_project(None, ctypes.byref(d), 4, rp.RP_OMEGA_F16, 0, 0, None, 4, None,
+                      rp.RP_ALGO_SPLIT_F16, 0, None, 4, None)
     assert st == rp.RP_ERR_INVALID_ARG
     assert b"ctx" in L.rp_last_error(None)
     assert L.rp_omega_generate(None, 0, 0, 4, 4, rp.RP_OMEGA_F16, None, 4, None) == rp.RP_ERR_INVALID_ARG

@@ -48,6 +48,27 @@ def test_c1_eckart_young_and_halko():
     assert np.mean(resid) <= rsvd.halko_bound(tail, k, s)
 
 
+def test_halko_bound_c1_value():
+    # eq:qqta-acc at the 1024^2 workload: p = 32, s = 32, ||Sigma_2||_F = 0.070897
+    sig = synth.sigma_geometric(1024, 0.9)
+    tail = float(np.sqrt((sig[32:] ** 2).sum()))
+    assert rsvd.halko_bound(tail, 32, 32) == pytest.approx(0.101068, abs=2e-6)
+
+
+@pytest.mark.parametrize("p,s", [(8, 5), (32, 32)])
+def test_halko_factor_is_gaussian_pinv_mean(p, s):
+    """eq:qqta-acc comes from eq:sgg: the excess over ||Sigma_2||_F^2 is
+    ||Sigma_2||_F^2 E||G_1^+||_F^2 with G_1 a p x (p + s) Gaussian matrix.
+    A Monte Carlo mean of ||G_1^+||_F^2 must match (bound / tail)^2 - 1, which
+    pins the p/(s-1) term and the square root independently of the formula."""
+    rng = np.random.default_rng(5)
+    n = 20000 if p < 16 else 4000
+    vals = np.array([np.sum(np.linalg.pinv(rng.standard_normal((p, p + s))) ** 2) for _ in range(n)])
+    mc, se = vals.mean(), vals.std() / np.sqrt(n)
+    factor = (rsvd.halko_bound(1.0, p, s)) ** 2 - 1.0
+    assert abs(mc - factor) <= 4 * se
+
+
 def test_power_iteration_sharpens():
     rng = np.random.default_rng(3)
     sig = 1.0 / np.arange(1, 201) ** 0.5
