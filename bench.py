@@ -264,28 +264,36 @@ def hosvd_leg(rp, synth, torch, dev):
             "device_status": rp.status_string(status)}
 
 
+def load_sigma64():
+    """(sigma, a_sha256) of the FP64 oracle's RSVD of the 32768^2 workload
+    (tests/golden/rsvd_32768_sigma64.txt), or (None, None)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "rsvd_32768_sigma64.txt")
+    if not os.path.exists(path):
+        return None, None
+    sha, vals = None, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# a_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.strip() and not line.startswith("#"):
+                vals.append(float(line))
+    return np.array(vals), sha
+
+
 def rsvd_leg(rp, synth, torch, dev):
     """Full randomized SVD: A 32768 x 32768 FP32 = U diag(sigma) V^T + noise,
     planted rank 512 with sigma_i = 10^(-(i-1)/511), noise N(0, (1e-4)^2);
     k = 512, oversampling 128 (Omega 32768 x 640 FP16), one power iteration,
-    CholeskyQR2 in FP64.  Wall time of rsvd() (inputs resident), and the
-    singular-value error against the planted values, bounded by Weyl's
-    inequality by ||E||_2 ~ 1e-4 * 2 sqrt(32768) = 0.036."""
-    import numpy as np
+    CholeskyQR2 in FP64.  Wall time of rsvd() (inputs resident); the
+    singular-value error against the FP64 oracle's RSVD of the same A with the
+    same Omega, and against the planted values (bounded by Weyl's inequality
+    by ||E||_2 ~ 1e-4 * 2 sqrt(32768) = 0.036)."""
+    import hashlib
     m = n = 32768
     k, s, q = 512, 128, 1
     t = time.time()
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(103)
-    sig = torch.tensor(10.0 ** (-np.arange(k) / (k - 1)), device=dev, dtype=torch.float64)
-    u = synth.torch_haar(m, k, gen, dev)
-    v = synth.torch_haar(n, k, gen, dev)
-    a = torch.empty((m, n), dtype=torch.float32, device=dev)
-    for r0 in range(0, m, 4096):                       # formed in FP64 row blocks
-        blk = (u[r0:r0 + 4096] * sig) @ v.T
-        blk += torch.randn(blk.shape, generator=gen, device=dev, dtype=torch.float64) * 1e-4
-        a[r0:r0 + 4096] = blk.float()
-    del u, v, blk
+    a, sig = synth.torch_rsvd_workload(dev, m, n, k)
     torch.cuda.synchronize()
     log(f"RSVD A generated in {time.time() - t:.1f} s")
     walls = []
@@ -297,14 +305,20 @@ def rsvd_leg(rp, synth, torch, dev):
         walls.append(time.perf_counter() - t0)
     status = rp.rp_get_device_status(clear=True)
     err = float((sv - sig).abs().max().item())
-    log(f"RSVD 32768^2 k=512: wall {walls}, max |sigma - planted| {err:.3e}")
+    sig64, sha = load_sigma64()
+    out = {"workload": "rsvd A 32768x32768 FP32 planted rank 512 (sigma_i=10^(-(i-1)/511)) + N(0,1e-4) noise; "
+                       "k=512, p=640, Omega FP16, q=1, CholeskyQR2 FP64",
+           "wall_s": round(min(walls), 4), "wall_s_first_call": round(walls[0], 4),
+           "max_abs_sigma_err_vs_planted": err, "weyl_bound": 1e-4 * 2 * math.sqrt(m)}
+    if sig64 is not None:
+        d = sv.double().cpu().numpy() - sig64
+        out["sigma_err_vs_fp64"] = {"max_abs": float(abs(d).max()), "max_rel": float((abs(d) / sig64).max()),
+                                    "same_A_as_oracle": hashlib.sha256(a.cpu().numpy().tobytes()).hexdigest() == sha}
+    out["device_status"] = rp.status_string(status)
+    log(f"RSVD 32768^2 k=512: wall {walls}, max |sigma - planted| {err:.3e}, vs FP64 {out.get('sigma_err_vs_fp64')}")
     del a, uu, vt
     torch.cuda.empty_cache()
-    return {"workload": "rsvd A 32768x32768 FP32 planted rank 512 (sigma_i=10^(-(i-1)/511)) + N(0,1e-4) noise; "
-                        "k=512, p=640, Omega FP16, q=1, CholeskyQR2 FP64",
-            "wall_s": round(min(walls), 4), "wall_s_first_call": round(walls[0], 4),
-            "max_abs_sigma_err_vs_planted": err, "weyl_bound": 1e-4 * 2 * math.sqrt(m),
-            "device_status": rp.status_string(status)}
+    return out
 
 
 def batched_leg(rp, synth, torch, dev):

@@ -118,3 +118,25 @@ def torch_planted(m, n, sigma, seed, device, noise_std=0.0):
         del blk
     del u, v, us, vt
     return a
+
+
+def torch_rsvd_workload(device, m=32768, n=32768, k=512, noise_std=1e-4, seed=103):
+    """The full randomized-SVD workload: FP32 A = U diag(sigma) V^T + E with
+    planted rank k, sigma_i = 10^(-(i-1)/(k-1)), Haar U, V and E ~ N(0,
+    noise_std^2), formed in FP64 row blocks on ``device``.  Returns (A,
+    sigma) with sigma the planted values (FP64)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    sig = torch.tensor(10.0 ** (-np.arange(k) / (k - 1)), device=device, dtype=torch.float64)
+    u = torch_haar(m, k, gen, device)
+    v = torch_haar(n, k, gen, device)
+    a = torch.empty((m, n), dtype=torch.float32, device=device)
+    for r0 in range(0, m, 4096):
+        blk = (u[r0:r0 + 4096] * sig) @ v.T
+        blk += torch.randn(blk.shape, generator=gen, device=device, dtype=torch.float64) * noise_std
+        a[r0:r0 + 4096] = blk.float()
+        del blk
+    del u, v
+    return a, sig
+
