@@ -215,12 +215,15 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
  *     Q = QR(Y);  B = Q^T A;  U', S, V' = SVD(B);  U = Q U'[:, :k].
  * Omega is generated from (seed, stream_id 0) in omega_type and the
  * projection runs with `algo` (RP_ALGO_SPLIT_F16 is the paper's method;
- * RP_ALGO_F32 the baseline); A^T Q (power scheme and B) is a plain FP32
- * library GEMM (rocBLAS), the other products FP32 with FP64 accumulation.
- * Every QR is CholeskyQR2 with the Gram matrix, Cholesky
- * factor and triangular inverse in FP64; the SVD of B is taken as
- * B^T = Q_B R_B (CholeskyQR2) followed by a one-sided Jacobi SVD of R_B^T in
- * FP64.
+ * RP_ALGO_F32 the baseline); A^T Q (power scheme and B) and A W run on this
+ * library's FP32 matrix-core kernels, the products with the small factors in
+ * FP32 with FP64 accumulation.  Every QR is CholeskyQR2 with the Gram
+ * matrix, Cholesky factor and triangular inverse in FP64; the SVD of B is
+ * taken as B^T = Q_B R_B (CholeskyQR2) followed by a one-sided Jacobi SVD of
+ * R_B^T in FP64 (at most 16 sweeps).  Outside stream capture the call reads a
+ * 4-byte convergence flag back after every Jacobi sweep (synchronising
+ * `stream`) and stops sweeping once it is set; under capture every sweep is
+ * recorded and the sweeps after convergence do no work.
  * Outputs (device): U m x k (ldu >= k), S k doubles in descending order, VT
  * k x n (ldvt >= n).  Singular vectors are determined up to sign.
  * a_scale_exp applies to the projection Y = A Omega as in rp_project().
@@ -231,8 +234,9 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
  * needed (allocating and synchronising the device then).  Otherwise `work`
  * (device, caller-owned, 256-byte aligned, contents undefined on entry) must
  * hold at least the bytes rsvd_workspace_size() reports for the same
- * arguments; the call then allocates nothing and does not synchronise, and
- * the caller keeps `work` alive until the work on `stream` has finished.
+ * arguments; the call then allocates nothing and synchronises only for the
+ * Jacobi flag, and the caller keeps `work` alive until the work on `stream`
+ * has finished.
  */
 rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda,
                int64_t k, int64_t oversample, int32_t power_iters,

@@ -605,7 +605,7 @@ hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t 
 }
 
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
-                            double tol, unsigned int* status, hipStream_t s) {
+                            double tol, unsigned int* status, hipStream_t s, const int* poll_flag) {
     if (count <= 0 || max_n <= 0) return hipSuccess;
     hipError_t e;
     const int gx = grid1d((int64_t)max_n * max_n) < 1024 ? grid1d((int64_t)max_n * max_n) : 1024;
@@ -621,6 +621,12 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
         hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, tab,
                            count, sweep);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (poll_flag) {   // one problem, not captured: stop once its converged flag is set
+            int done = 0;
+            if ((e = hipMemcpyAsync(&done, poll_flag, sizeof done, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            if (done) break;
+        }
     }
     hipLaunchKernelGGL(jacobi_final_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab, status);
     return hipGetLastError();

@@ -814,8 +814,13 @@ rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_pro
     rp_status st;
     if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s)) != RP_OK) return st;
     RP_HIP(ctx, rpmi::launch_set_jacobi_prob(w.jtab, rpmi::JacobiProb{w.MW, w.MV, (int)p, 0, w.jflags}, s));
+    // outside graph capture the sweeps stop at convergence (the host polls the
+    // converged flag once per sweep); under capture all sweeps are recorded and
+    // a converged problem's kernels return at once
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    RP_HIP(ctx, hipStreamIsCapturing(s, &cap));
     RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,
-                                       ctx->d_status, s));
+                                       ctx->d_status, s, cap == hipStreamCaptureStatusNone ? w.jflags : nullptr));
     return rsvd_after_svd(ctx, q, p, w, s);
 }
 

@@ -169,8 +169,11 @@ struct JacobiProb {
 };
 // Write one Jacobi table entry from the kernel arguments (no host copy).
 hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStream_t s);
+// poll_flag != NULL (a single problem, stream not being captured): the
+// host reads that device flag (the problem's flags[0], "converged") after
+// every sweep, synchronising the stream, and stops issuing sweeps once set.
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
-                            double tol, unsigned int* status, hipStream_t s);
+                            double tol, unsigned int* status, hipStream_t s, const int* poll_flag = nullptr);
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
 

@@ -81,3 +81,44 @@ def test_rsvd_invalid_arguments():
     a = torch.ones((50, 40), device="cuda")
     with pytest.raises(rp().RpError):
         rp().rsvd(a, 30, 20)          # k + s > min(m, n)
+
+
+def _golden_sigma64():
+    """FP64 oracle singular values of the 32768^2 workload and the SHA-256 of
+    the A they were computed from (tests/golden/make_rsvd_sigma64.py)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rsvd_32768_sigma64.txt")
+    sha, vals = None, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# a_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.strip() and not line.startswith("#"):
+                vals.append(float(line))
+    return np.array(vals), sha
+
+
+def test_rsvd_full_size_vs_fp64_oracle():
+    """The 32768^2 workload (planted rank 512 + N(0, 1e-8) noise; k = 512,
+    p = 640, one power step, FP16 Omega from seed 203) against the FP64
+    oracle's singular values of the same A with the same Omega (stored by
+    tests/golden/make_rsvd_sigma64.py, which calls only the oracle on the A
+    drawn by synth).  Bound: the FP32 products A^T Q and Q^T A contract over
+    m = 32768 rows, so each sigma_i moves by at most about gamma_m(2^-24) ||A||_2
+    per product (Weyl); two such products give 2 gamma_m(2^-24) sigma_1."""
+    import hashlib
+    import torch
+    from oracle import project
+    announce("rsvd 32768^2 k=512 q=1 vs the FP64 oracle's sigma")
+    sig64, sha = _golden_sigma64()
+    a, _ = synth.torch_rsvd_workload("cuda")
+    assert hashlib.sha256(a.cpu().numpy().tobytes()).hexdigest() == sha, "A differs from the oracle's input"
+    _, sv, _ = rp().rsvd(a, 512, 128, 1, 203, "f16", "split_f16")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    sv = host(sv)
+    del a
+    torch.cuda.empty_cache()
+    tol = 2.0 * project.gamma(32768, 2.0 ** -24) * sig64[0]
+    err = np.abs(sv - sig64)
+    print(f"max |sigma - sigma64| {err.max():.3e} (bound {tol:.3e}), max relative {(err / sig64).max():.3e}")
+    assert err.max() <= tol
