@@ -206,6 +206,26 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
                             rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy, void* stream);
 
 /*
+ * rp_project_packed() for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, validation and result as rp_project_packed()
+ * (bit for bit: the same kernels and the same contraction split), but the
+ * partial sums and arrival counters of the contraction split live in one
+ * static device array of the library (64 MiB of partial sums + 4 KiB of
+ * counters) that each device holds until the process ends; no device memory
+ * is allocated, and nothing synchronises.  A shape whose split needs more
+ * than that returns RP_ERR_INVALID_ARG before anything is enqueued (the
+ * planner never asks for more than 64 MiB on a device of up to 256 compute
+ * units).  Each call first clears the counters it uses with a kernel.  All
+ * calls on one device share the array and it keeps the last call's
+ * contents: calls that overlap in time on one device (any contexts, any
+ * streams) race and give undefined results.
+ */
+rp_status rp_project_packed_noalloc(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
+                                    rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy,
+                                    void* stream);
+
+/*
  * Randomized SVD (Algorithm 1, Sec. 2.2) of the m x n FP32 matrix A (row-major,
  * leading dimension lda >= n), with target rank k and oversampling s
  * (p = k + s columns of Omega, 1 <= k <= p <= min(m, n), p <= 1024) and

@@ -78,6 +78,7 @@ def lib():
         "rp_omega_packed_size": [i64, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
         "rp_omega_pack": [vp, u64, u32, vp, i64, vp, i32, i64, i64, i32, vp, vp],
         "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, i32, vp, i64, vp],
+        "rp_project_packed_noalloc": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, i32, vp, i64, vp],
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
         "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, i32, vp, i64, vp, vp, i64, vp,
                  ctypes.c_size_t, vp],
@@ -230,6 +231,17 @@ def rp_project_packed(a, r, packed, algo="split_f16", y=None, desc=None, a_scale
     ldy = y.stride(0) if y.numel() else max(r, 1)
     _check(ctx.handle, lib().rp_project_packed(ctx.handle, ctypes.byref(d), r, _ptr(packed),
                                                ALGOS[algo], int(a_scale_exp), _ptr(y), ldy, _stream()))
+    return y
+
+
+def rp_project_packed_noalloc(a, r, packed, y, algo="split_f16", desc=None, a_scale_exp=0, ctx=None):
+    """rp_project_packed into a caller-allocated y, with the library's static
+    scratch instead of any device allocation."""
+    ctx = ctx or default_context()
+    d = desc if desc is not None else desc_from_tensor(a)
+    ldy = y.stride(0) if y.numel() else max(r, 1)
+    _check(ctx.handle, lib().rp_project_packed_noalloc(ctx.handle, ctypes.byref(d), r, _ptr(packed), ALGOS[algo],
+                                                       int(a_scale_exp), _ptr(y), ldy, _stream()))
     return y
 
 

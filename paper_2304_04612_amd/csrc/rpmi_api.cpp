@@ -31,6 +31,9 @@ struct rp_ctx_s {
     unsigned int* split_counters = nullptr;   // per-tile arrival counters: zero
     size_t split_counter_bytes = 0;           // between launches (reset by each tile's last workgroup)
     int num_cus = 0;
+    // device address of the no-allocation scratch array on this device
+    // (hipGetSymbolAddress at creation; never the array's host-side name)
+    unsigned char* noalloc_scratch = nullptr;
     std::string last_error;
     // batched RSVD: the captured graph of the last problem set (replayed while
     // the set, its buffers and the context buffers are unchanged), its own
@@ -174,6 +177,12 @@ rp_status rp_create(rp_ctx* out, int device) {
     if ((e = hipMemset(ctx->d_status, 0, sizeof(unsigned int))) != hipSuccess) return cleanup(e, "hipMemset");
     if ((e = hipMalloc(&ctx->table, 64 * sizeof(rpmi::GroupEntry))) != hipSuccess) return cleanup(e, "hipMalloc");
     ctx->table_entries = 64;
+    {
+        void* p = nullptr;
+        if ((e = rpmi::noalloc_scratch_address(&p)) != hipSuccess || !p)
+            return cleanup(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        ctx->noalloc_scratch = static_cast<unsigned char*>(p);
+    }
     *out = ctx;
     return RP_OK;
 }
@@ -599,6 +608,48 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
     if (!proj_layout_ok(ctx, A, &st)) return st;
     return launch_projection(ctx, A, r, packed_geometry(n, r, algo, const_cast<void*>(packed)), algo, Y, ldy, s,
                              algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0);
+}
+
+rp_status rp_project_packed_noalloc(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
+                                    rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy, void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    rp_status st;
+    if (!desc_ok(ctx, A, &st)) return st;
+    if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16)
+        return fail(ctx, RP_ERR_INVALID_ARG, "unknown algorithm %d", (int)algo);
+    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
+    if (r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative r %lld", (long long)r);
+    const int64_t m = A->rows, n = A->cols;
+    if (m == 0 || r == 0) return RP_OK;
+    if (!Y) return fail(ctx, RP_ERR_INVALID_ARG, "Y is NULL");
+    if (ldy < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldy %lld < r %lld", (long long)ldy, (long long)r);
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    if (n == 0) {
+        RP_HIP(ctx, rpmi::launch_fill_f32(Y, m, r, ldy, 0.0f, s));
+        return RP_OK;
+    }
+    if (!packed) return fail(ctx, RP_ERR_INVALID_ARG, "packed is NULL");
+    if (!proj_layout_ok(ctx, A, &st)) return st;
+    SplitBuffers sb{reinterpret_cast<unsigned int*>(ctx->noalloc_scratch + rpmi::kNoAllocPartialBytes),
+                    reinterpret_cast<float*>(ctx->noalloc_scratch), rpmi::kNoAllocCounterBytes,
+                    rpmi::kNoAllocPartialBytes};
+    if (algo == RP_ALGO_SPLIT_F16) {
+        const rpmi::SplitPlan plan = rpmi::plan_split_f16(m, n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
+        if (plan.ksplit > 1) {
+            if (plan.partial_bytes > sb.partial_bytes || plan.counter_bytes > sb.counter_bytes)
+                return fail(ctx, RP_ERR_INVALID_ARG,
+                            "the contraction split of this shape needs %zu bytes of partial sums and %zu of "
+                            "counters; the no-allocation scratch holds %zu and %zu",
+                            plan.partial_bytes, plan.counter_bytes, sb.partial_bytes, sb.counter_bytes);
+            // the counters must start at zero: cleared by a kernel (not a
+            // memset node) so the call can be captured into a graph
+            RP_HIP(ctx, rpmi::launch_fill_u32(sb.counters, (int64_t)(plan.counter_bytes / sizeof(unsigned int)), 0u,
+                                              s));
+        }
+    }
+    return launch_projection(ctx, A, r, packed_geometry(n, r, algo, const_cast<void*>(packed)), algo, Y, ldy, s,
+                             algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, false, &sb);
 }
 
 rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_type, uint64_t seed,

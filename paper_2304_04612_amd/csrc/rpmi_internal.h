@@ -90,6 +90,16 @@ struct SplitPlan {
 };
 SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus);
 
+// Scratch of the no-allocation projection entry point (one static device
+// array per device): partial sums first, then the arrival counters.  The
+// planner never gives tiles x ksplit more workgroups than compute units, and
+// a tile is at most 256 x 256 floats, so the partial sums of any split fit
+// in num_cus x 256 KiB: 64 MiB on a 256-CU device.
+constexpr size_t kNoAllocPartialBytes = size_t(64) << 20;
+constexpr size_t kNoAllocCounterBytes = 4096;
+// Device address of that array on the current device.
+hipError_t noalloc_scratch_address(void** out);
+
 constexpr unsigned int kStatusRange = 1u;
 constexpr unsigned int kStatusNotSpd = 2u;
 constexpr unsigned int kStatusNotConverged = 4u;
