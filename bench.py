@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--no-rsvd", action="store_true", help="skip the 32768^2 randomized SVD")
     p.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched RSVD")
     p.add_argument("--no-hosvd", action="store_true", help="skip the 512^3 RP-HOSVD")
+    p.add_argument("--no-accuracy", action="store_true", help="skip the 4096^2 accuracy suites")
     p.add_argument("--a-cache", default=None,
                    help="file holding A (raw FP32, row-major); written on first use, read afterwards")
     return p.parse_args()
@@ -201,7 +202,42 @@ def main():
         out["batched_rsvd"] = batched_leg(rp, synth, torch, dev)
     if not args.no_hosvd:
         out["rp_hosvd"] = hosvd_leg(rp, synth, torch, dev)
+    if not args.no_accuracy:
+        out["accuracy_suites"] = accuracy_leg(rp, synth, torch, dev)
     print(json.dumps(out), flush=True)
+
+
+def accuracy_leg(rp, synth, torch, dev, seeds=(1, 2, 3)):
+    """The accuracy experiment of the randomized SVD: 4096 x 4096 FP32
+    A_linear and A_exp (s_p = 1e-3), A_Poly (r = 20, alpha = 3, phi = 1e6) and
+    A_Cauchy (one step of orthogonal iteration), target rank 256, oversampling
+    10: mean relative residual ||A - U S V^T||_F / ||A||_F over the seeds for
+    the split-FP16 path and the FP32 path, beside the Eckart-Young optimum."""
+    import numpy as np
+    n, p, s_over = 4096, 256, 10
+    res = {}
+    for kind in ("linear", "exp", "poly", "cauchy"):
+        acc = {"split_f16": [], "f32": [], "optimum": []}
+        for seed in seeds:
+            if kind == "cauchy":
+                a = torch.from_numpy(synth.np_cauchy(n, np.random.default_rng(seed))).to(dev)
+                sv_all = torch.linalg.svdvals(a.double())
+                opt = float((sv_all[p:].norm() / sv_all.norm()).item())
+            else:
+                sv = {"linear": synth.sv_linear(n, p, 1e-3), "exp": synth.sv_exp(n, p, 1e-3),
+                      "poly": synth.sv_poly(n, 20, 3.0, 1e6)}[kind]
+                a = synth.torch_sv_matrix(n, sv, seed, dev)
+                opt = float(np.sqrt(np.sum(sv[p:] ** 2) / np.sum(sv ** 2)))
+            ad = a.double()
+            for omega_type, algo in (("f16", "split_f16"), ("f32", "f32")):
+                u, s, vt = rp.rsvd(a, p, s_over, 1 if kind == "cauchy" else 0, 100 + seed, omega_type, algo)
+                rec = (u.double() * s[None, :]) @ vt.double()
+                acc[algo].append(float(((ad - rec).norm() / ad.norm()).item()))
+            acc["optimum"].append(opt)
+        res[kind] = {k: float(np.mean(v)) for k, v in acc.items()}
+        log(f"accuracy {kind}: {res[kind]}")
+    return {"workload": "rsvd 4096^2 FP32, target rank 256, oversampling 10, seeds " + str(list(seeds)),
+            "mean_rel_residual": res, "device_status": rp.status_string(rp.rp_get_device_status(clear=True))}
 
 
 def hosvd_leg(rp, synth, torch, dev):

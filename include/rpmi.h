@@ -251,7 +251,8 @@ rp_status rp_project_packed_noalloc(rp_ctx ctx, const rp_desc* A, int64_t r, con
  * Y numerically rank-deficient beyond FP64 Gram range), RP_ERR_NOT_CONVERGED
  * (Jacobi), RP_ERR_RANGE (split path, 2^s A outside FP16 range).
  * Workspace: with work == NULL the context workspace is used and grown as
- * needed (allocating and synchronising the device then).  Otherwise `work`
+ * needed (allocating and synchronising the device then), and the packed
+ * Omega comes from the context cache described at rp_hosvd().  Otherwise `work`
  * (device, caller-owned, 256-byte aligned, contents undefined on entry) must
  * hold at least the bytes rsvd_workspace_size() reports for the same
  * arguments; the call then allocates nothing and synchronises only for the
@@ -363,7 +364,10 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
  * dims, ranks, factors: host arrays owned by the caller, read during the call.
  * Device conditions: RP_ERR_NOT_SPD (a W_i numerically rank-deficient),
  * RP_ERR_RANGE (split path, X outside the FP16 range).  Grows the context
- * workspace as needed (synchronising the device then).
+ * workspace as needed (synchronising the device then).  The packed Omega_i
+ * are kept in a context cache (up to 1 GiB, least recently used freed first,
+ * the device synchronised before a free) keyed by (seed, stream_id, n, r,
+ * omega_type, algo), so a repeated call generates no Omega; a miss allocates.
  */
 rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X,
                    const int64_t* ranks, uint64_t seed, rp_omega_t omega_type,

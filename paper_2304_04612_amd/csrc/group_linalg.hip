@@ -1,0 +1,312 @@
+// Grouped (table-driven) linear algebra for many small RSVD problems at once
+// (the batched randomized SVD: Algorithm 1 for every problem of a set).  Each
+// kernel reads a device table of jobs and runs all of them in one launch, so
+// that a stage of Algorithm 1 costs one launch for the whole set instead of
+// one (or a dozen) per problem:
+//
+// * gemm_acc64_group: C_g = alpha op(A_g) op(B_g) (+ beta C_g) with arbitrary
+//   strides and FP64 accumulation (64 x 64 output tiles); blocks find their
+//   job by binary search over each job's first block.  Used for the Gram
+//   matrices Y^T Y, the products Y R^-1 of CholeskyQR2, U = Q U_r, V = W V_r
+//   and the product of the two Cholesky factors.
+// * chol_inv_group: for every p x p FP64 Gram matrix G (p <= kCholGroupMaxP)
+//   the lower Cholesky factor L (G = L L^T) and X = L^-1, one workgroup per
+//   job with L held in LDS as a packed lower triangle.  A non-positive pivot
+//   sets NOT_SPD and the factorisation continues on |pivot|.
+// * gemm_tn_f32_group: C_g = A_g^T Q_g on FP32 MFMA for any leading
+//   dimensions (16-byte loads where rows are 16-byte aligned, element loads
+//   otherwise).
+// * svd_finish_group: singular values of W (column norms after the Jacobi
+//   iteration), their descending order, S, and the gathered U_r, V_r.
+#include "rpmi_internal.h"
+
+namespace rpmi {
+namespace {
+
+constexpr int GT = 64;      // output tile of gemm_acc64_group
+constexpr int GK = 16;      // contraction slice
+
+template <class T>
+__device__ __forceinline__ double ldd(const T* p) { return (double)*p; }
+
+__device__ __forceinline__ int find_job(const int64_t* starts, int count, int64_t b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(256) void gemm_acc64_group_kernel(const GemmJob* __restrict__ jobs,
+                                                               const int64_t* __restrict__ starts, int count) {
+    const int64_t blk = blockIdx.x;
+    const GemmJob J = jobs[find_job(starts, count, blk)];
+    const int64_t local = blk - J.start;
+    const int64_t ti = local / J.tiles_n, tj = local % J.tiles_n;
+    const TA* a = static_cast<const TA*>(J.a);
+    const TB* b = static_cast<const TB*>(J.b);
+    TC* c = static_cast<TC*>(J.c);
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    const int64_t i0 = ti * GT, j0 = tj * GT;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < J.K; k0 += GK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + q * 256;
+            int ii, kk;
+            if (J.sak == 1) { kk = e % GK; ii = e / GK; } else { ii = e % GT; kk = e / GT; }
+            const int64_t gi = i0 + ii, gk = k0 + kk;
+            As[kk][ii] = (gi < J.M && gk < J.K) ? ldd(a + gi * J.sam + gk * J.sak) : 0.0;
+            int jj, kb;
+            if (J.sbn == 1) { jj = e % GT; kb = e / GT; } else { kb = e % GK; jj = e / GK; }
+            const int64_t gj = j0 + jj, gkb = k0 + kb;
+            Bs[kb][jj] = (gj < J.N && gkb < J.K) ? ldd(b + gkb * J.sbk + gj * J.sbn) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { av[u] = As[kk][ty + 16 * u]; bv[u] = Bs[kk][tx + 16 * u]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
+            if (gi < J.M && gj < J.N) {
+                TC* dst = c + gi * J.scm + gj * J.scn;
+                const double old = J.beta != 0.0 ? (double)*dst : 0.0;
+                *dst = (TC)(J.alpha * acc[u][v] + J.beta * old);
+            }
+        }
+}
+
+// Packed lower triangle: element (i, l), l <= i, at i (i + 1) / 2 + l.
+__device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
+
+__global__ __launch_bounds__(256) void chol_inv_group_kernel(const CholJob* __restrict__ jobs, unsigned int* status) {
+    extern __shared__ double T[];
+    const CholJob J = jobs[blockIdx.x];
+    const int p = J.p, tid = threadIdx.x;
+    __shared__ double dsh;
+    for (int e = tid; e < p * (p + 1) / 2; e += 256) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (tri(i, 0) > e) --i;
+        while (tri(i + 1, 0) <= e) ++i;
+        const int l = e - tri(i, 0);
+        T[e] = J.G[(int64_t)i * p + l];
+    }
+    __syncthreads();
+    // right-looking Cholesky, one column per step
+    for (int j = 0; j < p; ++j) {
+        if (tid == 0) {
+            double v = T[tri(j, j)];
+            if (!(v > 0.0)) {
+                atomicOr(status, kStatusNotSpd);
+                v = fabs(v) > 0.0 ? fabs(v) : 1.0;
+            }
+            dsh = sqrt(v);
+            T[tri(j, j)] = dsh;
+        }
+        __syncthreads();
+        const double d = dsh;
+        for (int i = j + 1 + tid; i < p; i += 256) T[tri(i, j)] /= d;
+        __syncthreads();
+        const int w = p - j - 1;
+        for (int e = tid; e < w * w; e += 256) {
+            const int i = j + 1 + e / w, l = j + 1 + e % w;
+            if (l <= i) T[tri(i, l)] -= T[tri(i, j)] * T[tri(l, j)];
+        }
+        __syncthreads();
+    }
+    // L (zero above the diagonal) to L_out
+    for (int e = tid; e < p * p; e += 256) {
+        const int i = e / p, l = e % p;
+        J.L[e] = l <= i ? T[tri(i, l)] : 0.0;
+    }
+    // X = L^-1: thread c solves L x = e_c for column c, top to bottom
+    for (int cidx = tid; cidx < p; cidx += 256) {
+        for (int i = 0; i < cidx; ++i) J.X[(int64_t)i * p + cidx] = 0.0;
+        for (int i = cidx; i < p; ++i) {
+            double s = i == cidx ? 1.0 : 0.0;
+            for (int l = cidx; l < i; ++l) s -= T[tri(i, l)] * J.X[(int64_t)l * p + cidx];
+            J.X[(int64_t)i * p + cidx] = s / T[tri(i, i)];
+        }
+    }
+}
+
+// C (N x P) = A^T Q for A (K x N, lda) and Q (K x P, ldq) on
+// v_mfma_f32_16x16x4f32: the tiling of gemm_tn_f32 (a wave owns 64 x 64 of
+// C as 4 x 4 MFMA tiles with rows and columns permuted so that lane c reads
+// four consecutive elements of a row of A and of Q); VEC: those four are one
+// 16-byte load (lda, ldq, ldc multiples of 4 and 16-byte aligned bases).
+template <bool VEC>
+__global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
+                                                                const int64_t* __restrict__ starts, int count) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int64_t blk = blockIdx.x;
+    const TnJob J = jobs[find_job(starts, count, blk)];
+    const int64_t local = blk - J.start;
+    const int64_t bx = local % J.tiles_x, by = local / J.tiles_x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t i0 = (by * 4 + wave) * 64, j0 = bx * 64;
+    const int64_t ia = i0 + 4 * c, jq = j0 + 4 * c;
+    const bool a_full = ia + 3 < J.N, q_full = jq + 3 < J.P;
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    auto load4 = [](const float* row, int64_t col, int64_t lim, bool full) -> f4 {
+        if (VEC && full) return *reinterpret_cast<const f4*>(row + col);
+        f4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = col + e < lim ? row[col + e] : 0.0f;
+        return v;
+    };
+    for (int64_t k0 = 0; k0 < J.K; k0 += 16) {
+        f4 av[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + 4 * u + g;
+            const bool in = k < J.K;
+            av[u] = in ? load4(J.A + k * J.lda, ia, J.N, a_full) : f4{0.f, 0.f, 0.f, 0.f};
+            qv[u] = in ? load4(J.Q + k * J.ldq, jq, J.P, q_full) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + 4 * (4 * g + e) + a;
+            if (i >= J.N) continue;
+            float* crow = J.C + i * J.ldc;
+            if (VEC && q_full) {
+                *reinterpret_cast<f4*>(crow + jq) = f4{acc[a][0][e], acc[a][1][e], acc[a][2][e], acc[a][3][e]};
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (jq + b < J.P) crow[jq + b] = acc[a][b][e];
+            }
+        }
+}
+
+// sigma_j = |w_j| (column norms of W, row-major n x n); rank by sigma
+// descending (ties by index); S (first ncols), sigma and the order.  One
+// workgroup per job.
+__global__ __launch_bounds__(1024) void svd_sigma_group_kernel(const SvdJob* __restrict__ jobs) {
+    __shared__ double s[1024];
+    const SvdJob J = jobs[blockIdx.x];
+    const int n = J.n, tid = threadIdx.x;
+    for (int j = tid; j < n; j += blockDim.x) {
+        double a = 0.0;
+        for (int r = 0; r < n; ++r) a += J.W[(int64_t)r * n + j] * J.W[(int64_t)r * n + j];
+        s[j] = sqrt(a);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        int rank = 0;
+        for (int i = 0; i < n; ++i) rank += (s[i] > s[j]) || (s[i] == s[j] && i < j);
+        J.sig[rank] = s[j];
+        J.order[rank] = j;
+        if (rank < J.ncols) J.S[rank] = s[j];
+    }
+}
+
+// U_r[:, c] = W[:, order[c]] / sigma_c (0 when sigma_c == 0) and V_r[:, c] =
+// V[:, order[c]], both n x ncols; grid.y = job.
+__global__ void svd_gather_group_kernel(const SvdJob* __restrict__ jobs) {
+    const SvdJob J = jobs[blockIdx.y];
+    const int64_t total = (int64_t)J.n * J.ncols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / J.ncols), cidx = (int)(e % J.ncols);
+        const int src = J.order[cidx];
+        const double sg = J.sig[cidx];
+        J.Ur[e] = sg > 0.0 ? J.W[(int64_t)r * J.n + src] / sg : 0.0;
+        J.Vr[e] = J.V[(int64_t)r * J.n + src];
+    }
+}
+
+}  // namespace
+
+int64_t gemm_group_tiles(int64_t M, int64_t N) { return ((M + GT - 1) / GT) * ((N + GT - 1) / GT); }
+int64_t gemm_group_tiles_n(int64_t N) { return (N + GT - 1) / GT; }
+
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_acc64_group_kernel<TA, TB, TC>), dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
+                       count);
+    return hipGetLastError();
+}
+
+template hipError_t gemm_acc64_group<float, float, double>(const GemmJob*, const int64_t*, int, int64_t, hipStream_t);
+template hipError_t gemm_acc64_group<double, double, double>(const GemmJob*, const int64_t*, int, int64_t,
+                                                             hipStream_t);
+template hipError_t gemm_acc64_group<float, double, double>(const GemmJob*, const int64_t*, int, int64_t,
+                                                            hipStream_t);
+template hipError_t gemm_acc64_group<double, double, float>(const GemmJob*, const int64_t*, int, int64_t,
+                                                            hipStream_t);
+template hipError_t gemm_acc64_group<float, double, float>(const GemmJob*, const int64_t*, int, int64_t, hipStream_t);
+
+hipError_t chol_inv_group(const CholJob* jobs, int count, int max_p, unsigned int* status, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (max_p > kCholGroupMaxP) return hipErrorInvalidValue;
+    const size_t lds = (size_t)max_p * (max_p + 1) / 2 * sizeof(double);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_group_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(chol_inv_group_kernel, dim3((unsigned)count), dim3(256), lds, s, jobs, status);
+    return hipGetLastError();
+}
+
+int64_t tn_group_tiles_x(int64_t P) { return (P + 63) / 64; }
+int64_t tn_group_tiles(int64_t N, int64_t P) { return ((P + 63) / 64) * ((N + 255) / 256); }
+
+hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
+                             hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    if (vec)
+        hipLaunchKernelGGL(gemm_tn_f32_group_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
+                           count);
+    else
+        hipLaunchKernelGGL(gemm_tn_f32_group_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
+                           count);
+    return hipGetLastError();
+}
+
+hipError_t svd_finish_group(const SvdJob* jobs, int count, int max_elems, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(svd_sigma_group_kernel, dim3((unsigned)count), dim3(1024), 0, s, jobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int gx = (max_elems + 255) / 256;
+    gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
+    hipLaunchKernelGGL(svd_gather_group_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+}  // namespace rpmi

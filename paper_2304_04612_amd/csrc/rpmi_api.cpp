@@ -45,7 +45,24 @@ struct rp_ctx_s {
     size_t graph_table_entries = 0;
     rpmi::JacobiProb* graph_jtab = nullptr;   // the batched Jacobi table read by the graph
     size_t graph_jtab_entries = 0;
+    char* graph_aux = nullptr;                // job tables of the grouped stages read by the graph
+    size_t graph_aux_bytes = 0;
     std::unordered_map<uint64_t, double> tuned_scale;
+    // generated Omega kept in device memory, keyed by what defines its bits
+    // (seed, stream_id, n, r, type) and by the fragment format (algorithm);
+    // least recently used entries are freed beyond kOmegaCacheBytes
+    struct OmegaEntry {
+        uint64_t seed;
+        uint32_t stream_id;
+        int64_t n, r;
+        int type, algo;
+        void* data;
+        size_t bytes;
+        uint64_t last_use;
+    };
+    std::vector<OmegaEntry> omega_cache;
+    size_t omega_cache_bytes = 0;
+    uint64_t omega_tick = 0;
 };
 
 namespace {
@@ -202,6 +219,8 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
     if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
+    if (ctx->graph_aux) (void)hipFree(ctx->graph_aux);
+    for (auto& e : ctx->omega_cache) (void)hipFree(e.data);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RP_OK;
@@ -348,6 +367,52 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
     RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, src_f32, scratch, r, s));
     RP_HIP(ctx, rpmi::launch_pack_omega(scratch, src_f32 ? rpmi::OmegaSrc::F32 : rpmi::OmegaSrc::F16, nullptr, n, r, r,
                                         pk, true, nullptr, 0, nullptr, s));
+    return RP_OK;
+}
+
+// Generated Omega from the context cache (a1: Omega depends only on seed,
+// stream, n, r and type, so repeated calls reuse the packed fragments).  On a
+// miss the fragments are generated into a new cache allocation (scratch: the
+// generator's row-major staging), evicting least recently used entries
+// beyond kOmegaCacheBytes; the device is synchronised before any free.
+// Returns RP_ERR_UNSUPPORTED (nothing done) for an Omega larger than the
+// cache.
+constexpr size_t kOmegaCacheBytes = size_t(1) << 30;
+
+rp_status cached_packed_omega(rp_ctx ctx, uint64_t seed, uint32_t stream_id, rp_omega_t type, int64_t n, int64_t r,
+                              rp_algo_t algo, void* scratch, hipStream_t s, rpmi::PackedOmega* pk) {
+    *pk = packed_geometry(n, r, algo, nullptr);
+    const size_t bytes = packed_bytes(*pk, algo);
+    for (auto& e : ctx->omega_cache)
+        if (e.seed == seed && e.stream_id == stream_id && e.n == n && e.r == r && e.type == (int)type &&
+            e.algo == (int)algo) {
+            e.last_use = ++ctx->omega_tick;
+            pk->data = e.data;
+            return RP_OK;
+        }
+    if (bytes == 0 || bytes > kOmegaCacheBytes) return RP_ERR_UNSUPPORTED;
+    if (ctx->omega_cache_bytes + bytes > kOmegaCacheBytes) {
+        RP_HIP(ctx, hipDeviceSynchronize());
+        while (ctx->omega_cache_bytes + bytes > kOmegaCacheBytes) {
+            size_t lru = 0;
+            for (size_t i = 1; i < ctx->omega_cache.size(); ++i)
+                if (ctx->omega_cache[i].last_use < ctx->omega_cache[lru].last_use) lru = i;
+            RP_HIP(ctx, hipFree(ctx->omega_cache[lru].data));
+            ctx->omega_cache_bytes -= ctx->omega_cache[lru].bytes;
+            ctx->omega_cache.erase(ctx->omega_cache.begin() + lru);
+        }
+    }
+    void* data = nullptr;
+    RP_HIP(ctx, hipMalloc(&data, bytes));
+    pk->data = data;
+    rp_status st = fill_packed(ctx, seed, stream_id, nullptr, 0, nullptr, type, n, r, algo, *pk, scratch, s);
+    if (st != RP_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(data);
+        return st;
+    }
+    ctx->omega_cache.push_back({seed, stream_id, n, r, (int)type, (int)algo, data, bytes, ++ctx->omega_tick});
+    ctx->omega_cache_bytes += bytes;
     return RP_OK;
 }
 
@@ -903,6 +968,203 @@ RsvdPlan rsvd_plan(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64_t oversamp
     return pl;
 }
 
+// ------------------------------------------------------------------ grouped batched stages
+// Host image of the job tables of the grouped kernels (group_linalg.hip) for
+// one batched call; uploaded once per captured graph into ctx->graph_aux.
+struct AuxImage {
+    std::vector<char> bytes;
+    size_t add(const void* p, size_t n) {
+        const size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + n);
+        memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+};
+
+struct GemmStage {
+    size_t jobs = 0, starts = 0;
+    int count = 0;
+    int64_t blocks = 0;
+};
+
+GemmStage add_gemm_stage(AuxImage& im, std::vector<rpmi::GemmJob> jobs) {
+    GemmStage st;
+    std::vector<int64_t> starts(jobs.size());
+    int64_t b = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        jobs[i].tiles_n = rpmi::gemm_group_tiles_n(jobs[i].N);
+        jobs[i].start = b;
+        starts[i] = b;
+        b += rpmi::gemm_group_tiles(jobs[i].M, jobs[i].N);
+    }
+    st.count = (int)jobs.size();
+    st.blocks = b;
+    if (!jobs.empty()) {
+        st.jobs = im.add(jobs.data(), jobs.size() * sizeof(rpmi::GemmJob));
+        st.starts = im.add(starts.data(), starts.size() * sizeof(int64_t));
+    }
+    return st;
+}
+
+rpmi::GemmJob gemm_job(int64_t M, int64_t N, int64_t K, const void* a, int64_t sam, int64_t sak, const void* b,
+                       int64_t sbk, int64_t sbn, void* c, int64_t scm, int64_t scn) {
+    rpmi::GemmJob j{};
+    j.M = M; j.N = N; j.K = K;
+    j.alpha = 1.0; j.beta = 0.0;
+    j.a = a; j.sam = sam; j.sak = sak;
+    j.b = b; j.sbk = sbk; j.sbn = sbn;
+    j.c = c; j.scm = scm; j.scn = scn;
+    return j;
+}
+
+struct CholStage {
+    size_t jobs = 0;
+    int count = 0, max_p = 0;
+};
+
+// CholeskyQR2 of every problem's Y (rows R_g x p_g, FP32, ld p_g) into Q
+// (FP32, ld p_g), with scratch from its RsvdScratch; with_m: also M = L1 L2
+// (into MW), the lower factor R^T of the triangular factor R.
+struct CholQr2Group {
+    GemmStage gram1, qd, gram2, q, m;
+    CholStage chol1, chol2;
+    bool with_m = false;
+};
+
+CholQr2Group build_cholqr2_group(AuxImage& im, const std::vector<int64_t>& rows, const std::vector<float*>& Y,
+                                 const std::vector<float*>& Q, const std::vector<RsvdScratch>& ws, bool with_m) {
+    const size_t n = ws.size();
+    std::vector<rpmi::GemmJob> g1, qd, g2, qq, mm;
+    std::vector<rpmi::CholJob> c1, c2;
+    CholQr2Group G;
+    G.with_m = with_m;
+    for (size_t i = 0; i < n; ++i) {
+        const RsvdScratch& w = ws[i];
+        const int64_t p = w.p, R = rows[i];
+        g1.push_back(gemm_job(p, p, R, Y[i], 1, p, Y[i], p, 1, w.G, p, 1));
+        c1.push_back(rpmi::CholJob{w.G, with_m ? w.L1 : w.G, w.X, (int)p});
+        qd.push_back(gemm_job(R, p, p, Y[i], p, 1, w.X, 1, p, w.Qd, p, 1));
+        g2.push_back(gemm_job(p, p, R, w.Qd, 1, p, w.Qd, p, 1, w.G, p, 1));
+        c2.push_back(rpmi::CholJob{w.G, w.G, w.X, (int)p});
+        qq.push_back(gemm_job(R, p, p, w.Qd, p, 1, w.X, 1, p, Q[i], p, 1));
+        if (with_m) mm.push_back(gemm_job(p, p, p, w.L1, p, 1, w.G, p, 1, w.MW, p, 1));
+        G.chol1.max_p = G.chol2.max_p = (int)p > G.chol1.max_p ? (int)p : G.chol1.max_p;
+    }
+    G.gram1 = add_gemm_stage(im, g1);
+    G.chol1.jobs = im.add(c1.data(), n * sizeof(rpmi::CholJob));
+    G.chol1.count = (int)n;
+    G.qd = add_gemm_stage(im, qd);
+    G.gram2 = add_gemm_stage(im, g2);
+    G.chol2.jobs = im.add(c2.data(), n * sizeof(rpmi::CholJob));
+    G.chol2.count = (int)n;
+    G.q = add_gemm_stage(im, qq);
+    if (with_m) G.m = add_gemm_stage(im, mm);
+    return G;
+}
+
+template <class TA, class TB, class TC>
+hipError_t run_gemm_stage(const GemmStage& st, char* aux, hipStream_t s) {
+    return rpmi::gemm_acc64_group<TA, TB, TC>(reinterpret_cast<const rpmi::GemmJob*>(aux + st.jobs),
+                                              reinterpret_cast<const int64_t*>(aux + st.starts), st.count, st.blocks,
+                                              s);
+}
+
+rp_status run_cholqr2_group(rp_ctx ctx, const CholQr2Group& G, char* aux, hipStream_t s) {
+    RP_HIP(ctx, (run_gemm_stage<float, float, double>(G.gram1, aux, s)));
+    RP_HIP(ctx, rpmi::chol_inv_group(reinterpret_cast<const rpmi::CholJob*>(aux + G.chol1.jobs), G.chol1.count,
+                                     G.chol1.max_p, ctx->d_status, s));
+    RP_HIP(ctx, (run_gemm_stage<float, double, double>(G.qd, aux, s)));
+    RP_HIP(ctx, (run_gemm_stage<double, double, double>(G.gram2, aux, s)));
+    RP_HIP(ctx, rpmi::chol_inv_group(reinterpret_cast<const rpmi::CholJob*>(aux + G.chol2.jobs), G.chol2.count,
+                                     G.chol2.max_p, ctx->d_status, s));
+    RP_HIP(ctx, (run_gemm_stage<double, double, float>(G.q, aux, s)));
+    if (G.with_m) RP_HIP(ctx, (run_gemm_stage<double, double, double>(G.m, aux, s)));
+    return RP_OK;
+}
+
+// Z_g = A_g^T Q_g for every problem, as two grouped launches: the jobs on the
+// 16-byte path and the others.
+struct TnGroup {
+    size_t jobs[2] = {0, 0}, starts[2] = {0, 0};
+    int count[2] = {0, 0};
+    int64_t blocks[2] = {0, 0};
+};
+
+TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::vector<RsvdScratch>& ws) {
+    TnGroup T;
+    std::vector<rpmi::TnJob> jobs[2];
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    for (size_t i = 0; i < ws.size(); ++i) {
+        const rp_rsvd_problem& q = probs[i];
+        const RsvdScratch& w = ws[i];
+        rpmi::TnJob j{};
+        j.N = q.n; j.P = w.p; j.K = q.m;
+        j.A = q.A; j.lda = q.lda; j.Q = w.Q; j.ldq = w.p; j.C = w.Z; j.ldc = w.p;
+        const bool vec = q.lda % 4 == 0 && w.p % 4 == 0 && al(q.A) && al(w.Q) && al(w.Z);
+        jobs[vec ? 1 : 0].push_back(j);
+    }
+    for (int v = 0; v < 2; ++v) {
+        std::vector<int64_t> starts(jobs[v].size());
+        int64_t b = 0;
+        for (size_t i = 0; i < jobs[v].size(); ++i) {
+            jobs[v][i].tiles_x = rpmi::tn_group_tiles_x(jobs[v][i].P);
+            jobs[v][i].start = b;
+            starts[i] = b;
+            b += rpmi::tn_group_tiles(jobs[v][i].N, jobs[v][i].P);
+        }
+        T.count[v] = (int)jobs[v].size();
+        T.blocks[v] = b;
+        if (!jobs[v].empty()) {
+            T.jobs[v] = im.add(jobs[v].data(), jobs[v].size() * sizeof(rpmi::TnJob));
+            T.starts[v] = im.add(starts.data(), starts.size() * sizeof(int64_t));
+        }
+    }
+    return T;
+}
+
+rp_status run_tn_group(rp_ctx ctx, const TnGroup& T, char* aux, hipStream_t s) {
+    for (int v = 0; v < 2; ++v)
+        if (T.count[v] > 0)
+            RP_HIP(ctx, rpmi::gemm_tn_f32_group(reinterpret_cast<const rpmi::TnJob*>(aux + T.jobs[v]),
+                                                reinterpret_cast<const int64_t*>(aux + T.starts[v]), T.count[v],
+                                                T.blocks[v], v == 1, s));
+    return RP_OK;
+}
+
+// After the grouped Jacobi: S, U = Q U_r[:, :k], V^T = (Q_B V_r[:, :k])^T.
+struct FinishGroup {
+    size_t svd = 0;
+    int count = 0, max_elems = 0;
+    GemmStage u, vt;
+};
+
+FinishGroup build_finish_group(AuxImage& im, const rp_rsvd_problem* probs, const std::vector<RsvdScratch>& ws) {
+    FinishGroup F;
+    std::vector<rpmi::SvdJob> sj;
+    std::vector<rpmi::GemmJob> uj, vj;
+    for (size_t i = 0; i < ws.size(); ++i) {
+        const rp_rsvd_problem& q = probs[i];
+        const RsvdScratch& w = ws[i];
+        const int64_t p = w.p, k = q.k;
+        sj.push_back(rpmi::SvdJob{w.MW, w.MV, (int)p, (int)k, w.sig, w.ord, q.S, w.Ur, w.Vr});
+        F.max_elems = (int)(p * k) > F.max_elems ? (int)(p * k) : F.max_elems;
+        uj.push_back(gemm_job(q.m, k, p, w.Q, p, 1, w.Ur, k, 1, q.U, q.ldu, 1));
+        vj.push_back(gemm_job(q.n, k, p, w.W, p, 1, w.Vr, k, 1, q.VT, 1, q.ldvt));
+    }
+    F.count = (int)sj.size();
+    F.svd = im.add(sj.data(), sj.size() * sizeof(rpmi::SvdJob));
+    F.u = add_gemm_stage(im, uj);
+    F.vt = add_gemm_stage(im, vj);
+    return F;
+}
+
+rp_status run_finish_group(rp_ctx ctx, const FinishGroup& F, char* aux, hipStream_t s) {
+    RP_HIP(ctx, rpmi::svd_finish_group(reinterpret_cast<const rpmi::SvdJob*>(aux + F.svd), F.count, F.max_elems, s));
+    RP_HIP(ctx, (run_gemm_stage<float, double, float>(F.u, aux, s)));
+    RP_HIP(ctx, (run_gemm_stage<float, double, float>(F.vt, aux, s)));
+    return RP_OK;
+}
+
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
     return h;
@@ -957,9 +1219,16 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
                     pl.sp.counter_bytes, pl.sp.partial_bytes};
     if (pl.sp.counter_bytes)
         RP_HIP(ctx, rpmi::launch_fill_u32(sb.counters, (int64_t)(pl.sp.counter_bytes / 4), 0u, s));
-    // Algorithm 1 line 1: Y = A Omega
-    if ((st = fill_packed(ctx, seed, 0, nullptr, 0, nullptr, omega_type, n, p, algo, pk, base + pl.o_raw, s)) != RP_OK)
-        return st;
+    // Algorithm 1 line 1: Y = A Omega (Omega from the context cache, or
+    // generated into the workspace when it does not fit the cache or the
+    // caller's workspace rules out allocation)
+    st = work ? RP_ERR_UNSUPPORTED
+              : cached_packed_omega(ctx, seed, 0, omega_type, n, p, algo, base + pl.o_raw, s, &pk);
+    if (st == RP_ERR_UNSUPPORTED) {
+        pk.data = base + pl.o_pk;
+        st = fill_packed(ctx, seed, 0, nullptr, 0, nullptr, omega_type, n, p, algo, pk, base + pl.o_raw, s);
+    }
+    if (st != RP_OK) return st;
     if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, false,
                                 &sb)) != RP_OK)
         return st;
@@ -1172,6 +1441,39 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     }
     rpmi::JacobiProb* jtab = ctx->graph_jtab;
     RP_HIP(ctx, hipMemcpy(jtab, jt.data(), jt.size() * sizeof(rpmi::JacobiProb), hipMemcpyHostToDevice));
+    // every stage after the projections as grouped launches when every
+    // problem's Cholesky factor fits the one-workgroup kernel
+    const bool grouped_stages = mp <= rpmi::kCholGroupMaxP;
+    AuxImage im;
+    CholQr2Group cq_yq, cq_zw, cq_zw_m;
+    TnGroup tn;
+    FinishGroup fin;
+    if (grouped_stages) {
+        std::vector<int64_t> mrows(count), nrows(count);
+        std::vector<float*> ys(count), qs(count), zs(count), wsp(count);
+        for (int32_t g = 0; g < count; ++g) {
+            mrows[g] = probs[g].m;
+            nrows[g] = probs[g].n;
+            ys[g] = reinterpret_cast<float*>(base + o_y[g]);
+            qs[g] = ws[g].Q;
+            zs[g] = ws[g].Z;
+            wsp[g] = ws[g].W;
+        }
+        cq_yq = build_cholqr2_group(im, mrows, ys, qs, ws, false);
+        if (power_iters > 0) cq_zw = build_cholqr2_group(im, nrows, zs, wsp, ws, false);
+        cq_zw_m = build_cholqr2_group(im, nrows, zs, wsp, ws, true);
+        tn = build_tn_group(im, probs, ws);
+        fin = build_finish_group(im, probs, ws);
+        if (im.bytes.size() > ctx->graph_aux_bytes) {
+            if (ctx->graph_aux) RP_HIP(ctx, hipFree(ctx->graph_aux));
+            ctx->graph_aux = nullptr;
+            ctx->graph_aux_bytes = 0;
+            RP_HIP(ctx, hipMalloc(&ctx->graph_aux, im.bytes.size()));
+            ctx->graph_aux_bytes = im.bytes.size();
+        }
+        RP_HIP(ctx, hipMemcpy(ctx->graph_aux, im.bytes.data(), im.bytes.size(), hipMemcpyHostToDevice));
+    }
+    char* aux = ctx->graph_aux;
     RP_HIP(ctx, hipDeviceSynchronize());
 
     // capture: Omega generation, the grouped projections, then every
@@ -1207,15 +1509,39 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                 return r2;
             }
         }
-        for (int32_t g = 0; g < count; ++g) {
-            const rp_rsvd_problem& q = probs[g];
-            const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
-            r2 = rsvd_before_svd(ctx, dA, q, q.k + q.oversample, power_iters, reinterpret_cast<float*>(base + o_y[g]),
-                                 ws[g], cs);
-            if (r2 != RP_OK) return r2;
+        if (grouped_stages) {
+            // Algorithm 1 lines 2-4 for every problem at once (power scheme:
+            // the products A W stay per problem)
+            for (int32_t t = 0; t < power_iters; ++t) {
+                if ((r2 = run_cholqr2_group(ctx, cq_yq, aux, cs)) != RP_OK) return r2;
+                if ((r2 = run_tn_group(ctx, tn, aux, cs)) != RP_OK) return r2;
+                if ((r2 = run_cholqr2_group(ctx, cq_zw, aux, cs)) != RP_OK) return r2;
+                for (int32_t g = 0; g < count; ++g) {
+                    const rp_rsvd_problem& q = probs[g];
+                    const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+                    const int64_t p = q.k + q.oversample;
+                    RP_HIP(ctx, rpmi::launch_pack_omega(ws[g].W, rpmi::OmegaSrc::F32, nullptr, q.n, p, p, ws[g].pkw,
+                                                        true, nullptr, 0, nullptr, cs));
+                    if ((r2 = launch_projection(ctx, &dA, p, ws[g].pkw, RP_ALGO_F32,
+                                                reinterpret_cast<float*>(base + o_y[g]), p, cs)) != RP_OK)
+                        return r2;
+                }
+            }
+            if ((r2 = run_cholqr2_group(ctx, cq_yq, aux, cs)) != RP_OK) return r2;
+            if ((r2 = run_tn_group(ctx, tn, aux, cs)) != RP_OK) return r2;
+            if ((r2 = run_cholqr2_group(ctx, cq_zw_m, aux, cs)) != RP_OK) return r2;
+        } else {
+            for (int32_t g = 0; g < count; ++g) {
+                const rp_rsvd_problem& q = probs[g];
+                const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
+                r2 = rsvd_before_svd(ctx, dA, q, q.k + q.oversample, power_iters,
+                                     reinterpret_cast<float*>(base + o_y[g]), ws[g], cs);
+                if (r2 != RP_OK) return r2;
+            }
         }
         // one parallel Jacobi SVD over every problem's R_B^T
         RP_HIP(ctx, rpmi::jacobi_svd_group(jtab, count, jpairs, (int)mp, kJacobiSweeps, kJacobiTol, ctx->d_status, cs));
+        if (grouped_stages) return run_finish_group(ctx, fin, aux, cs);
         for (int32_t g = 0; g < count; ++g)
             if ((r2 = rsvd_after_svd(ctx, probs[g], probs[g].k + probs[g].oversample, ws[g], cs)) != RP_OK) return r2;
         return RP_OK;
@@ -1328,14 +1654,17 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     // copied mode-first into one scratch tensor (one mode at a time, so those
     // projections run separately).
     for (int i = 0; i < N; ++i) {
-        pk[i].data = base + o_pk[i];
         W[i] = reinterpret_cast<float*>(base + o_w[i]);
         ldw[i] = ranks[i];
         dp[i] = &desc[i];
         const int64_t cols = total / dims[i];
-        if ((st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, pk[i],
-                              base + o_raw, s)) != RP_OK)
-            return st;
+        st = cached_packed_omega(ctx, seed, (uint32_t)i, omega_type, cols, ranks[i], algo, base + o_raw, s, &pk[i]);
+        if (st == RP_ERR_UNSUPPORTED) {
+            pk[i].data = base + o_pk[i];
+            st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, pk[i],
+                             base + o_raw, s);
+        }
+        if (st != RP_OK) return st;
     }
     bool grouped_done = false;
     if (algo == RP_ALGO_SPLIT_F16) {

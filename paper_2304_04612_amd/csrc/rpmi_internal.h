@@ -187,6 +187,63 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
 
+// ---------------------------------------------------------------- group_linalg.hip
+// Job tables of the grouped kernels (device memory; every job of a launch is
+// independent).  `start` is the job's first block and the launch's `starts`
+// array repeats it, sorted, for the blocks' binary search.
+struct GemmJob {                      // C = alpha op(A) op(B) + beta C, FP64 accumulation
+    int64_t M, N, K;
+    double alpha, beta;
+    const void* a;
+    int64_t sam, sak;
+    const void* b;
+    int64_t sbk, sbn;
+    void* c;
+    int64_t scm, scn;
+    int64_t tiles_n, start;
+};
+int64_t gemm_group_tiles(int64_t M, int64_t N);
+int64_t gemm_group_tiles_n(int64_t N);
+template <class TA, class TB, class TC>
+hipError_t gemm_acc64_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s);
+
+constexpr int kCholGroupMaxP = 199;   // p (p + 1) / 2 doubles of L fit in 160 KiB of LDS
+struct CholJob {                      // G (p x p) = L L^T; L (lower, zero above) and X = L^-1
+    const double* G;
+    double* L;                        // may equal G
+    double* X;
+    int p;
+};
+hipError_t chol_inv_group(const CholJob* jobs, int count, int max_p, unsigned int* status, hipStream_t s);
+
+struct TnJob {                        // C (N x P) = A^T Q, A K x N, Q K x P, all FP32 row-major
+    int64_t N, P, K;
+    const float* A;
+    int64_t lda;
+    const float* Q;
+    int64_t ldq;
+    float* C;
+    int64_t ldc;
+    int64_t tiles_x, start;
+};
+int64_t tn_group_tiles_x(int64_t P);
+int64_t tn_group_tiles(int64_t N, int64_t P);
+// vec: every job has 16-byte aligned A, Q, C and lda, ldq, ldc multiples of 4
+hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
+                             hipStream_t s);
+
+struct SvdJob {                       // after the Jacobi iteration on W (n x n) with V
+    const double* W;
+    const double* V;
+    int n, ncols;
+    double* sig;                      // n, descending
+    int* order;                       // n
+    double* S;                        // ncols (the caller's output)
+    double* Ur;                       // n x ncols
+    double* Vr;                       // n x ncols
+};
+hipError_t svd_finish_group(const SvdJob* jobs, int count, int max_elems, hipStream_t s);
+
 }  // namespace rpmi
 
 extern "C" int rpmi_build_f16_thresholds(uint64_t* table, int capacity);

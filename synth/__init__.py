@@ -15,6 +15,8 @@ method).  Two back ends draw the same *distributions*:
 Workloads (the paper's experiments are synthetic throughout):
   planted spectrum  A = U diag(sigma) V^T with Haar-distributed U, V
                     (Sec. 3.3 type 2; Sec. 5.1.1 use slatms for the same role)
+  accuracy suites   A_linear, A_exp, A_Poly (= Type 2), Type 1, A_Cauchy
+                    (Sec. 3.3, Sec. 5.1.1)
   tucker            core x_1 U_1 x_2 U_2 x_3 U_3 + noise (Sec. 5.2, Alg. 3 role)
 """
 import math
@@ -73,6 +75,58 @@ def np_tucker(dims, core_dims, rng, noise_std=0.0):
     if noise_std:
         x = x + noise_std * rng.standard_normal(dims)
     return np.ascontiguousarray(x, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------- accuracy suites
+# Singular-value sequences and matrices of the paper's accuracy experiments
+# (Sec. 3.3: Type 1 / Type 2; Sec. 5.1.1: A_linear, A_exp, A_Poly, A_Cauchy).
+# The paper forms the prescribed-spectrum matrices with LAPACK slatms; here
+# they are U diag(s) V^T with Haar U, V (the same law for the spectrum).
+
+def sv_linear(n, p, s_p):
+    """s_i = max(1 - alpha_l i, s_p), alpha_l = (1 - s_p) / p, i = 0 .. n-1."""
+    i = np.arange(n, dtype=np.float64)
+    return np.maximum(1.0 - (1.0 - s_p) / p * i, s_p)
+
+
+def sv_exp(n, p, s_p):
+    """s_i = 2^(-alpha_e i), alpha_e = log2(1 / s_p) / p, i = 0 .. n-1."""
+    i = np.arange(n, dtype=np.float64)
+    return 2.0 ** (-(np.log2(1.0 / s_p) / p) * i)
+
+
+def sv_poly(n, r, alpha, phi):
+    """Type 2 spectrum: phi (r times), then 2^-alpha, 3^-alpha, ..., (n - r + 1)^-alpha."""
+    tail = np.arange(2, n - r + 2, dtype=np.float64) ** (-alpha)
+    return np.concatenate([np.full(r, float(phi)), tail])
+
+
+def np_type1(n, r, xi, rng):
+    """Type 1: A = diag(I_r, 0) + (xi / n) G G^T with G an n x n Gaussian
+    matrix (the noise scale xi / eps with eps read as n), FP32."""
+    g = rng.standard_normal((n, n))
+    a = (xi / n) * (g @ g.T)
+    a[np.arange(r), np.arange(r)] += 1.0
+    return a.astype(np.float32)
+
+
+def np_cauchy(n, rng, gamma=1e-3, width=1e-3):
+    """A_ij = 1 / (|x_i - y_j| + gamma) with x, y ~ U(-width, width), FP32
+    (the paper's A_Cauchy with its |x_i - y_i| read as |x_i - y_j|)."""
+    x = rng.uniform(-width, width, n)
+    y = rng.uniform(-width, width, n)
+    return (1.0 / (np.abs(x[:, None] - y[None, :]) + gamma)).astype(np.float32)
+
+
+def torch_sv_matrix(n, s, seed, device):
+    """FP32 n x n matrix U diag(s) V^T with Haar U, V, drawn on ``device``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    sig = torch.as_tensor(np.asarray(s, np.float64), device=device)
+    u = torch_haar(n, n, gen, device)
+    v = torch_haar(n, n, gen, device)
+    return ((u * sig[None, :]) @ v.T).to(torch.float32)
 
 
 def batched_problem_list(count, seed, lo=512, hi=8192, kmin=16, kmax=128):

@@ -1,0 +1,117 @@
+"""The paper's accuracy experiments on the GPU path.
+
+* Sec. 5.1.1: randomized SVD of 4096 x 4096 FP32 A_linear, A_exp, A_Poly and
+  A_Cauchy with target rank p = 256 and oversampling s = 10 (A_Cauchy with one
+  step of orthogonal iteration).  The paper's finding is that the split-FP16
+  projection keeps RSVD at the accuracy of the FP32 path: here the relative
+  residual ||A - U S V^T||_F / ||A||_F of the split path is within 5% of the
+  FP32 path's (FP32 Omega, FP32 kernel), and neither beats the Eckart-Young
+  optimum (Theorem eym), computed from the prescribed singular values.
+* Sec. 3.3: the projection error ||A - Q Q^T A||_F with Omega in FP16 and in
+  e4m3 (a 3-bit mantissa) is at the level of the FP32 Omega, for Type 1 and
+  Type 2 inputs (n = 4096, r = 20, Omega with r + 10 columns).
+
+A_Cauchy stays inside the FP16 range here (1/(|x - y| + 1e-3) <= 1000), so
+the split path does not report RP_ERR_RANGE on it."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, rp
+
+pytestmark = pytest.mark.gpu
+
+N, P, S = 4096, 256, 10
+
+
+def _residual(a, u, sv, vt):
+    import torch
+    ad = a.double()
+    rec = (u.double() * sv[None, :]) @ vt.double()
+    return float(((ad - rec).norm() / ad.norm()).item())
+
+
+def _suite_matrix(kind, seed):
+    import torch
+    if kind == "linear":
+        s = synth.sv_linear(N, P, 1e-3)
+    elif kind == "exp":
+        s = synth.sv_exp(N, P, 1e-3)
+    elif kind == "poly":
+        s = synth.sv_poly(N, 20, 3.0, 1e6)
+    else:
+        a = torch.from_numpy(synth.np_cauchy(N, np.random.default_rng(seed))).cuda()
+        return a, None
+    return synth.torch_sv_matrix(N, s, seed, "cuda"), s
+
+
+@pytest.mark.parametrize("kind", ["linear", "exp", "poly", "cauchy"])
+def test_rsvd_accuracy_suite(kind):
+    q = 1 if kind == "cauchy" else 0
+    for seed in (1, 2):
+        announce(f"accuracy suite {kind} seed {seed}")
+        a, s = _suite_matrix(kind, seed)
+        res = {}
+        for omega_type, algo in (("f16", "split_f16"), ("f32", "f32")):
+            u, sv, vt = rp().rsvd(a, P, S, q, 100 + seed, omega_type, algo)
+            assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+            res[algo] = _residual(a, u, sv, vt)
+        if s is not None:
+            opt = float(np.sqrt(np.sum(s[P:] ** 2)) / np.sqrt(np.sum(s ** 2)))
+        else:
+            import torch
+            sv_all = torch.linalg.svdvals(a.double())
+            opt = float((sv_all[P:].norm() / sv_all.norm()).item())
+        print(f"{kind} seed {seed}: residual split {res['split_f16']:.6e}  f32 {res['f32']:.6e}  optimum {opt:.6e}")
+        assert res["split_f16"] <= 1.05 * res["f32"] + 1e-7
+        assert res["split_f16"] >= opt * (1 - 1e-4) and res["f32"] >= opt * (1 - 1e-4)
+
+
+@pytest.mark.parametrize("kind", ["type1", "type2"])
+def test_projection_mantissa_study(kind):
+    """Sec. 3.3's experiment: the projection error with Gaussian matrices of
+    shorter mantissas, computed in FP64 so that only Omega's format matters
+    (the library's Omega in FP32, FP16 and e4m3, widened exactly); then the
+    library's own projections of the same A, whose rounding must not cost
+    accuracy (the split path within 5% of the FP32 path, or better)."""
+    import torch
+    n, r = N, 20
+    announce(f"mantissa study {kind}")
+    if kind == "type1":
+        a = torch.from_numpy(synth.np_type1(n, r, 1e-4, np.random.default_rng(11))).cuda()
+    else:
+        a = synth.torch_sv_matrix(n, synth.sv_poly(n, r, 3.0, 1e6), 12, "cuda")
+    ad = a.double()
+
+    def err(y):
+        qm, _ = torch.linalg.qr(y.double())
+        return float(((ad - qm @ (qm.T @ ad)).norm() / ad.norm()).item())
+
+    om = {"f32": rp().rp_omega_generate(n, r + 10, 31, 0, "f32").double(),
+          "f16": rp().rp_omega_generate(n, r + 10, 31, 0, "f16").view(torch.float16).double()}
+    codes, scale = rp().rp_omega_generate_e4m3(n, r + 10, 31, 0)
+    om["e4m3"] = torch.from_numpy(_e4m3_values(host_codes(codes), host_codes(scale))).cuda()
+    e64 = {t: err(ad @ o) for t, o in om.items()}
+    print(f"{kind}: FP64 projection, ||A - QQ^T A||_F / ||A||_F with Omega f32 {e64['f32']:.6e} "
+          f"f16 {e64['f16']:.6e} e4m3 {e64['e4m3']:.6e}")
+    for t in ("f16", "e4m3"):
+        assert 0.8 * e64["f32"] <= e64[t] <= 1.25 * e64["f32"], t
+    e_split = err(rp().rp_project(a, r + 10, seed=31, omega_type="f16", algo="split_f16"))
+    e_f32 = err(rp().rp_project(a, r + 10, seed=31, omega_type="f16", algo="f32"))
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    print(f"{kind}: library projection (FP16 Omega): split {e_split:.6e}  FP32 kernel {e_f32:.6e}")
+    assert e_split <= 1.05 * e_f32 + 1e-12
+
+
+def host_codes(t):
+    return t.detach().cpu().numpy()
+
+
+def _e4m3_values(codes, scale):
+    """Omega8 / s_j as FP64 (the values the projection uses): E4M3FN codes
+    decoded by the format's definition (bias 7, 3 mantissa bits, subnormals
+    at exponent field 0; the generator never emits the NaN codes)."""
+    c = codes.astype(np.int64)
+    e, m = (c >> 3) & 0xF, c & 7
+    mag = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * 2.0 ** (e - 7.0))
+    return np.where(c & 0x80, -mag, mag) / scale[None, :].astype(np.float64)

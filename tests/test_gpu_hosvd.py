@@ -200,3 +200,22 @@ def test_hosvd_e4m3_omega():
     for i, (q, q_o) in enumerate(zip(qs, qs_o)):
         assert _rel(q, q_o) < 2e-4, i
     assert _rel(ohosvd.reconstruct(g, qs), x.astype(np.float64)) < 5e-5
+
+
+def test_hosvd_omega_cache_repeat():
+    """Repeated calls reuse the context's cached Omega_i: the same seed gives
+    the same bits as the first (generating) call, and another seed (another
+    cache key) gives the other Omega's result, still matching the oracle."""
+    dims, core_dims = (40, 48, 36), (5, 6, 4)
+    announce(f"hosvd Omega cache {dims}")
+    x = synth.np_tucker(dims, core_dims, np.random.default_rng(8), noise_std=1e-3)
+    ranks = (8, 9, 7)
+    g1, q1, st1 = _gpu(x, ranks, 91, "f16", "split_f16")
+    g2, q2, st2 = _gpu(x, ranks, 91, "f16", "split_f16")
+    assert st1 == st2 == rp().RP_OK
+    assert np.array_equal(g1, g2) and all(np.array_equal(a, b) for a, b in zip(q1, q2))
+    g3, q3, st3 = _gpu(x, ranks, 92, "f16", "split_f16")
+    assert st3 == rp().RP_OK and not np.array_equal(g1, g3)
+    g_o, qs_o = _oracle(x, ranks, 92, "f16")
+    rec, rec_o = ohosvd.reconstruct(g3, q3), ohosvd.reconstruct(g_o, qs_o)
+    assert _rel(rec, rec_o) < 1e-3
