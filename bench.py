@@ -31,8 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # WRITE_SIZE) and scaled by the same counters on a copy of known size; valid
 # only while the kernel sources hash to the value recorded with it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "project_split_f16_16384x16384x256_hbm_traffic.txt")
-KERNEL_SOURCES = ("paper_2304_04612_amd/csrc/proj_common.h", "paper_2304_04612_amd/csrc/project_wide.hip",
-                  "paper_2304_04612_amd/csrc/rpmi_internal.h")
+KERNEL_SOURCES = ("paper_2304_04612_amd/csrc/proj_common.h", "paper_2304_04612_amd/csrc/proj_lds.h",
+                  "paper_2304_04612_amd/csrc/project_wide.hip", "paper_2304_04612_amd/csrc/rpmi_internal.h")
 
 
 def parse():
@@ -168,7 +168,7 @@ def main():
                                "Haar U,V), Omega 16384x256 FP16 (Philox4x64 + exact FP16 inverse CDF)",
                    "m": M, "n": N, "r": R, "seed_A": SEED_A, "seed_omega": SEED_OMEGA},
         "roofline": {
-            "kernel": "project_split_f16_single_kernel (256-column tile)",
+            "kernel": "project_split_lds_single_kernel (256-column tile)",
             "bound": "hbm",
             "achieved": round(alg_bytes / kern_s / 1e9, 1),
             "peak": HBM_PEAK_GBS,

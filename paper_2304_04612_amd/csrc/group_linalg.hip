@@ -5,7 +5,7 @@
 // one (or a dozen) per problem:
 //
 // * gemm_acc64_group: C_g = alpha op(A_g) op(B_g) (+ beta C_g) with arbitrary
-//   strides and FP64 accumulation (64 x 64 output tiles); blocks find their
+//   strides and FP64 MFMA products (64 x 64 output tiles); blocks find their
 //   job by binary search over each job's first block.  Used for the Gram
 //   matrices Y^T Y, the products Y R^-1 of CholeskyQR2, U = Q U_r, V = W V_r
 //   and the product of the two Cholesky factors.
@@ -19,15 +19,12 @@
 // * svd_finish_group: singular values of W (column norms after the Jacobi
 //   iteration), their descending order, S, and the gathered U_r, V_r.
 #include "rpmi_internal.h"
+#include "gemm64_tile.h"
 
 namespace rpmi {
 namespace {
 
-constexpr int GT = 64;      // output tile of gemm_acc64_group
-constexpr int GK = 16;      // contraction slice
-
-template <class T>
-__device__ __forceinline__ double ldd(const T* p) { return (double)*p; }
+constexpr int GT = kG64Tile;   // output tile of gemm_acc64_group
 
 __device__ __forceinline__ int find_job(const int64_t* starts, int count, int64_t b) {
     int lo = 0, hi = count - 1;
@@ -46,52 +43,9 @@ __global__ __launch_bounds__(256) void gemm_acc64_group_kernel(const GemmJob* __
     const GemmJob J = jobs[find_job(starts, count, blk)];
     const int64_t local = blk - J.start;
     const int64_t ti = local / J.tiles_n, tj = local % J.tiles_n;
-    const TA* a = static_cast<const TA*>(J.a);
-    const TB* b = static_cast<const TB*>(J.b);
-    TC* c = static_cast<TC*>(J.c);
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int64_t i0 = ti * GT, j0 = tj * GT;
-    double acc[4][4] = {};
-    for (int64_t k0 = 0; k0 < J.K; k0 += GK) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + q * 256;
-            int ii, kk;
-            if (J.sak == 1) { kk = e % GK; ii = e / GK; } else { ii = e % GT; kk = e / GT; }
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            As[kk][ii] = (gi < J.M && gk < J.K) ? ldd(a + gi * J.sam + gk * J.sak) : 0.0;
-            int jj, kb;
-            if (J.sbn == 1) { jj = e % GT; kb = e / GT; } else { kb = e % GK; jj = e / GK; }
-            const int64_t gj = j0 + jj, gkb = k0 + kb;
-            Bs[kb][jj] = (gj < J.N && gkb < J.K) ? ldd(b + gkb * J.sbk + gj * J.sbn) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) { av[u] = As[kk][ty + 16 * u]; bv[u] = Bs[kk][tx + 16 * u]; }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
-            if (gi < J.M && gj < J.N) {
-                TC* dst = c + gi * J.scm + gj * J.scn;
-                const double old = J.beta != 0.0 ? (double)*dst : 0.0;
-                *dst = (TC)(J.alpha * acc[u][v] + J.beta * old);
-            }
-        }
+    gemm64_tile<TA, TB, TC>(J.M, J.N, J.K, J.alpha, static_cast<const TA*>(J.a), J.sam, J.sak,
+                            static_cast<const TB*>(J.b), J.sbk, J.sbn, J.beta, static_cast<TC*>(J.c), J.scm, J.scn,
+                            ti * GT, tj * GT);
 }
 
 // Packed lower triangle: element (i, l), l <= i, at i (i + 1) / 2 + l.

@@ -5,8 +5,9 @@
 // throughout (the Gram of the skinny Y is formed in FP64 from FP32 data).
 //
 // * gemm_acc64: C = alpha * op(A) op(B) (+ beta C) with arbitrary row/column
-//   strides for every operand, FP64 accumulation, 64x64 output tiles staged
-//   through LDS in 16-deep slices; deterministic (fixed summation order).
+//   strides for every operand, FP64 products on v_mfma_f64_16x16x4f64, 64x64
+//   output tiles staged through LDS in 16-deep slices; deterministic (fixed
+//   summation order).
 // * Cholesky (lower, in place): blocked right-looking, 64-wide blocks: the
 //   diagonal block is factored in LDS by one workgroup, the panel below is
 //   solved against it, the trailing matrix is updated with gemm_acc64.  A
@@ -21,75 +22,28 @@
 //   off-diagonal above the tolerance in a whole sweep).
 // * C = A^T Q on FP32 MFMA; Gram products split along the contraction.
 #include "rpmi_internal.h"
+#include "gemm64_tile.h"
 
 namespace rpmi {
 namespace {
 
-constexpr int GT = 64;      // output tile
-constexpr int GK = 16;      // contraction slice
+constexpr int GT = kG64Tile;   // output tile
+constexpr int GK = kG64K;     // contraction slice
 constexpr int NB = 64;      // block size of the factorizations
 
 template <class T>
 __device__ __forceinline__ double ld(const T* p) { return (double)*p; }
 
-// C[i][j] = alpha * sum_k A(i,k) B(k,j) + beta * C[i][j], A(i,k) = a[i*sam + k*sak],
-// B(k,j) = b[k*sbk + j*sbn], C[i][j] = c[i*scm + j*scn].  beta == 0 ignores C's
-// old contents (NaN included).  256 threads, each owning a 4x4 block of the
-// 64x64 tile.
-// Batched over blockIdx.z: problem z uses a + z*sab, b + z*sbb, c + z*scb.
+// C[i][j] = alpha * sum_k A(i,k) B(k,j) + beta * C[i][j] on FP64 MFMA (one
+// 64 x 64 tile per workgroup, gemm64_tile.h), batched over blockIdx.z:
+// problem z uses a + z*sab, b + z*sbb, c + z*scb.
 template <class TA, class TB, class TC>
 __global__ __launch_bounds__(256) void gemm_acc64_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ a, int64_t sam, int64_t sak,
     const TB* __restrict__ b, int64_t sbk, int64_t sbn, double beta, TC* __restrict__ c, int64_t scm,
     int64_t scn, int64_t sab, int64_t sbb, int64_t scb) {
-    a += blockIdx.z * sab;
-    b += blockIdx.z * sbb;
-    c += blockIdx.z * scb;
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;       // 16 x 16 threads, 4x4 each
-    const int64_t i0 = blockIdx.y * (int64_t)GT, j0 = blockIdx.x * (int64_t)GT;
-    double acc[4][4] = {};
-    for (int64_t k0 = 0; k0 < K; k0 += GK) {
-        // stage 64x16 of A and 16x64 of B (4 elements per thread each)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + q * 256;          // 0..1023
-            // A: pick the mapping whose fastest index follows the unit stride
-            int ii, kk;
-            if (sak == 1) { kk = e % GK; ii = e / GK; } else { ii = e % GT; kk = e / GT; }
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            As[kk][ii] = (gi < M && gk < K) ? ld(a + gi * sam + gk * sak) : 0.0;
-            int jj, kb;
-            if (sbn == 1) { jj = e % GT; kb = e / GT; } else { kb = e % GK; jj = e / GK; }
-            const int64_t gj = j0 + jj, gkb = k0 + kb;
-            Bs[kb][jj] = (gj < N && gkb < K) ? ld(b + gkb * sbk + gj * sbn) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) { av[u] = As[kk][ty + 16 * u]; bv[u] = Bs[kk][tx + 16 * u]; }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
-            if (gi < M && gj < N) {
-                TC* dst = c + gi * scm + gj * scn;
-                const double old = beta != 0.0 ? (double)*dst : 0.0;
-                *dst = (TC)(alpha * acc[u][v] + beta * old);
-            }
-        }
+    gemm64_tile<TA, TB, TC>(M, N, K, alpha, a + blockIdx.z * sab, sam, sak, b + blockIdx.z * sbb, sbk, sbn, beta,
+                            c + blockIdx.z * scb, scm, scn, blockIdx.y * (int64_t)GT, blockIdx.x * (int64_t)GT);
 }
 
 // ---------------------------------------------------------------- Cholesky
@@ -306,18 +260,14 @@ __global__ void jacobi_prep_kernel(const JacobiProb* tab) {
     if (blockIdx.x == 0 && threadIdx.x < 4) P.flags[threadIdx.x] = 0;
 }
 
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab, int count, int round, int sweep,
-                                                           double tol) {
-    const int b = blockIdx.x;
+// One round: one wave per column pair (four pairs per workgroup), so the
+// three dot products of the pair's 2x2 Gram are reduced within the wave
+// (lane-strided partial sums, then a butterfly) with no workgroup barrier.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab, int count, int total_pairs,
+                                                           int round, int sweep, double tol) {
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= total_pairs) return;
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -336,15 +286,16 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     if (c >= n) return;                               // the dummy of an odd n
     double* wa = P.W + (int64_t)a * n;
     double* wc = P.W + (int64_t)c * n;
-    __shared__ double red[3][4];
     double al = 0.0, be = 0.0, ga = 0.0;
-    for (int r = threadIdx.x; r < n; r += 256) {
+    for (int r = lane; r < n; r += 64) {
         const double x = wa[r], y = wc[r];
         al += x * x; be += y * y; ga += x * y;
     }
-    al = block_sum256(al, red[0]);
-    be = block_sum256(be, red[1]);
-    ga = block_sum256(ga, red[2]);
+    for (int off = 32; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        ga += __shfl_xor(ga, off, 64);
+    }
     if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) return;
     // the rotation that zeroes the off-diagonal of the pair's 2x2 Gram
     const double zeta = (be - al) / (2.0 * ga);
@@ -352,7 +303,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
     double* va = P.V + (int64_t)a * n;
     double* vc = P.V + (int64_t)c * n;
-    for (int r = threadIdx.x; r < n; r += 256) {
+    for (int r = lane; r < n; r += 64) {
         const double x = wa[r], y = wc[r];
         wa[r] = cs * x - sn * y;
         wc[r] = sn * x + cs * y;
@@ -360,7 +311,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
         va[r] = cs * vx - sn * vy;
         vc[r] = sn * vx + cs * vy;
     }
-    if (threadIdx.x == 0) P.flags[1 + (sweep & 1)] = 1;
+    if (lane == 0) P.flags[1 + (sweep & 1)] = 1;
 }
 
 __global__ void set_jacobi_prob_kernel(JacobiProb* dst, JacobiProb v) {
@@ -614,8 +565,8 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
     const int max_m = max_n + (max_n & 1);
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int round = 0; round < max_m - 1; ++round) {
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)total_pairs), dim3(256), 0, s, tab, count, round,
-                               sweep, tol);
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)((total_pairs + 3) / 4)), dim3(256), 0, s, tab,
+                               count, total_pairs, round, sweep, tol);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, tab,

@@ -34,29 +34,8 @@ struct DmaCfg {
     using Tile = T;
     static constexpr int Depth = D;
 };
-#ifndef RPMI_WIDE_TM
-#define RPMI_WIDE_TM 2
-#endif
-#ifndef RPMI_WIDE_D
-#define RPMI_WIDE_D 6
-#endif
-#ifndef RPMI_NARROW_TM
-#define RPMI_NARROW_TM 2
-#endif
-#ifndef RPMI_NARROW_D
-#define RPMI_NARROW_D 6
-#endif
-using WideCfg = DmaCfg<Tile<4, 1, RPMI_WIDE_TM, 16, 1>, RPMI_WIDE_D>;      // r > 128: 256 columns
-using NarrowCfg = DmaCfg<Tile<4, 1, RPMI_NARROW_TM, 8, 1>, RPMI_NARROW_D>; // r <= 128: 128 columns
-using DmaTile = WideCfg::Tile;
+using NarrowCfg = DmaCfg<Tile<4, 1, 2, 8, 1>, 6>; // r <= 128: 128 columns, 6-step pipeline
 using DmaTile128 = NarrowCfg::Tile;
-#ifndef RPMI_TWO_ACC
-#define RPMI_TWO_ACC 0
-#endif
-#ifndef RPMI_KROT
-#define RPMI_KROT 0
-#endif
-constexpr bool kDmaTwoAcc = RPMI_TWO_ACC;   // one accumulator: hi against 2^11 Omega
 using F32Tile = Tile<2, 2, 4, 4, 1>;     // 128 x 128 outputs, 32-deep steps
 constexpr int kF32Depth = 3;
 
@@ -405,14 +384,12 @@ __device__ __forceinline__ void split_dma_body(const ProjArgs& p, const int64_t 
         constexpr int s = decltype(slot_c)::value;
         constexpr int cur = s & 1;
         wait_vm_barrier<(D - 3) * OPS>();
-        // a scheduling region every RPMI_STEP_REGION steps (the barrier above
+        // a scheduling region every kStepRegion steps (the barrier above
         // already orders the steps): larger regions schedule better, but the
         // interleaving solver's time grows steeply with the region (one region
         // per group of 6 steps takes minutes per instantiation)
-#ifndef RPMI_STEP_REGION
-#define RPMI_STEP_REGION 3
-#endif
-        if constexpr (RPMI_STEP_REGION > 0 && s % RPMI_STEP_REGION == 0) __builtin_amdgcn_sched_barrier(0);
+        constexpr int kStepRegion = 3;
+        if constexpr (s % kStepRegion == 0) __builtin_amdgcn_sched_barrier(0);
         issue(IntC<(s + D - 1) % D>{});
         mfma_step(hs[cur], ls[cur], stage_at(slot_c));
         split_step(ring[(s + 1) % D], hs[cur ^ 1], ls[cur ^ 1]);

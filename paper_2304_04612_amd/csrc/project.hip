@@ -22,7 +22,7 @@
 // step).  Rows beyond m are clamped for loads and masked for stores; a
 // contraction tail shorter than a step is loaded with per-element guards and
 // multiplies zero-padded Omega rows.
-#include "proj_common.h"
+#include "proj_lds.h"
 
 namespace rpmi {
 namespace {
@@ -37,6 +37,8 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
     const int g = lane >> 4, c = lane & 15;
     const int wm = wave % T::WM, wn = wave / T::WM;
     const int64_t bm = blockIdx.x, bn = blockIdx.y;
+    // recomputation after a folded launch: only the rows of marked blocks
+    if (p.fold_flags && p.fold_flags[((bm * T::BM) / WideCfg::BM) & (kFoldFlags - 1)] != p.fold_epoch) return;
 
     const AStream<T, VEC> as = make_astream<T, VEC>(p, bm, wm, c, g);
     const int64_t nsteps = as.nsteps;
@@ -268,12 +270,10 @@ int small_grid(int64_t total) {
 
 }  // namespace
 
-// Projections with r <= RPMI_NARROW_MAX use the 128-column tile (several
-// column tiles when r > 128); the packed Omega is padded to 128 columns for
-// r <= 128 and to 256 beyond.
-#ifndef RPMI_NARROW_MAX
-#define RPMI_NARROW_MAX 128
-#endif
+// Projections with r <= kNarrowMax use the 128-column tile, wider ones the
+// 256-column tile (several column tiles when r > 256); the packed Omega is
+// padded to 128 columns for r <= 128 and to multiples of 256 beyond.
+constexpr int64_t kNarrowMax = 128;
 int64_t split_f16_col_block(int64_t r) { return r <= 128 ? 128 : 256; }
 int64_t f32_col_block() { return F32Tile::BN; }
 int64_t proj_k_block() { return 64; }   // multiple of every tile's step (SplitTile 64, DmaTile 32, F32Tile 32)
@@ -288,14 +288,9 @@ SplitPlan plan_for(int64_t m, int64_t n, int64_t r, int num_cus) {
     const int64_t tiles = ((m + T::BM - 1) / T::BM) * ((r + T::BN - 1) / T::BN);
     const int64_t nfull = n / T::BK;
     if (tiles <= 0 || nfull <= 0) return plan;
-#ifndef RPMI_CU_OVERSUB
-#define RPMI_CU_OVERSUB 1
-#endif
-    int64_t k = RPMI_CU_OVERSUB * num_cus / tiles;   // fill the chip with tiles x k workgroups
-#ifndef RPMI_KSPLIT_MAX
-#define RPMI_KSPLIT_MAX 64
-#endif
-    k = k > RPMI_KSPLIT_MAX ? RPMI_KSPLIT_MAX : k;
+    int64_t k = num_cus / tiles;                    // fill the chip with tiles x k workgroups
+    constexpr int64_t kSplitMax = 64;
+    k = k > kSplitMax ? kSplitMax : k;
     k = k > nfull / (2 * C::Depth) ? nfull / (2 * C::Depth) : k;   // keep shares >= 2 groups
     if (k < 2) return plan;
     plan.ksplit = (int)k;
@@ -305,7 +300,7 @@ SplitPlan plan_for(int64_t m, int64_t n, int64_t r, int num_cus) {
 }
 
 SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
-    return r <= RPMI_NARROW_MAX ? plan_for<NarrowCfg>(m, n, r, num_cus) : plan_for<WideCfg>(m, n, r, num_cus);
+    return r <= kNarrowMax ? plan_for<NarrowCfg>(m, n, r, num_cus) : plan_for<WideCfg>(m, n, r, num_cus);
 }
 
 int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
@@ -317,29 +312,40 @@ hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, 
                   : launch_split_group_wide(table, count, blocks, one, s);
 }
 
-// The deep-pipeline kernel exists in grouped form only; a single projection
-// is a group of one passed by value.
+// A single projection on the 16-byte path goes to the fast kernel of its
+// width, passed by value (a group of one); other requests (caller pre-scale,
+// two accumulators, element loads) to the general kernel.  The wide fast
+// kernel takes the folded split: it marks the 256-row blocks it could not
+// take in a.fold_flags, and the general kernel then recomputes exactly those
+// rows (its blocks of other rows return at once).
 template <class C, class TS>
 hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
     using TD = typename C::Tile;
-    // the deep-pipeline kernel keeps one accumulator against 2^11 Omega and
-    // takes A unscaled; other requests go to the general kernel
+    dim3 grid((unsigned)((a.m + TS::BM - 1) / TS::BM), (unsigned)((a.r + TS::BN - 1) / TS::BN));
     if (split_fast_ok(a)) {
+        const bool wide = TD::BN != 128;
+        if (wide && (!a.fold_flags || a.fold_epoch == 0)) return hipErrorInvalidValue;
         GroupEntry e;
         e.p = a;
         e.tiles_m = (a.m + TD::BM - 1) / TD::BM;
         e.tiles_n = (a.r + TD::BN - 1) / TD::BN;
         e.start = 0;
-        return launch_project_split_f16_grouped(nullptr, 0, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
-                                                TD::BN == 128, s, &e);
+        hipError_t err = launch_project_split_f16_grouped(nullptr, 0, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
+                                                          !wide, s, &e);
+        if (err != hipSuccess || !wide) return err;
+        ProjArgs fb = a;
+        fb.ksplit = 1;
+        hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, true>), grid, dim3(TS::THREADS), 0, s, fb);
+        return hipGetLastError();
     }
-    dim3 grid((unsigned)((a.m + TS::BM - 1) / TS::BM), (unsigned)((a.r + TS::BN - 1) / TS::BN));
-    hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, false>), grid, dim3(TS::THREADS), 0, s, a);
+    ProjArgs g = a;
+    g.fold_flags = nullptr;
+    hipLaunchKernelGGL((project_split_f16_kernel<TS, kSplitDepth, false>), grid, dim3(TS::THREADS), 0, s, g);
     return hipGetLastError();
 }
 
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
-    return a.r <= RPMI_NARROW_MAX ? launch_split_with<NarrowCfg, SplitTile128>(a, s)
+    return a.r <= kNarrowMax ? launch_split_with<NarrowCfg, SplitTile128>(a, s)
                                   : launch_split_with<WideCfg, SplitTile>(a, s);
 }
 

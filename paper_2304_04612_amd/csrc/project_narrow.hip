@@ -10,10 +10,10 @@ hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t
     if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
     using T = NarrowCfg::Tile;
     if (one)
-        hipLaunchKernelGGL((project_split_f16_single_kernel<T, NarrowCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((project_split_f16_single_kernel<T, NarrowCfg::Depth, false>), dim3((unsigned)blocks),
                            dim3(T::THREADS), 0, s, one->p);
     else
-        hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, NarrowCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, NarrowCfg::Depth, false>), dim3((unsigned)blocks),
                            dim3(T::THREADS), 0, s, table, count);
     return hipGetLastError();
 }

@@ -1,20 +1,20 @@
-// The deep-pipeline split-FP16 projection for r > 128 (256-column tiles):
-// one instantiation of the grouped kernel, in a file of its own so that it
-// compiles in parallel with the other width.
-#include "proj_common.h"
+// The LDS-staged split-FP16 projection for r > 128 (256-column tiles): the
+// grouped (exact split) and single (folded split) forms, in a file of their
+// own so that they compile in parallel with the other width.
+#include "proj_lds.h"
 
 namespace rpmi {
 
 hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
-                                  hipStream_t s) {
+                                   hipStream_t s) {
     if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
-    using T = WideCfg::Tile;
+    using C = WideCfg;
     if (one)
-        hipLaunchKernelGGL((project_split_f16_single_kernel<T, WideCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
-                           dim3(T::THREADS), 0, s, one->p);
+        hipLaunchKernelGGL((project_split_lds_single_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                           one->p);
     else
-        hipLaunchKernelGGL((project_split_f16_grouped_kernel<T, WideCfg::Depth, kDmaTwoAcc>), dim3((unsigned)blocks),
-                           dim3(T::THREADS), 0, s, table, count);
+        hipLaunchKernelGGL((project_split_lds_grouped_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                           table, count);
     return hipGetLastError();
 }
 

@@ -34,6 +34,10 @@ struct rp_ctx_s {
     // device address of the no-allocation scratch array on this device
     // (hipGetSymbolAddress at creation; never the array's host-side name)
     unsigned char* noalloc_scratch = nullptr;
+    // flag table of the folded split (kFoldFlags words, zeroed at creation)
+    // and the launch epoch written into it (never 0)
+    unsigned int* fold_flags = nullptr;
+    unsigned int fold_epoch = 0;
     std::string last_error;
     // batched RSVD: the captured graph of the last problem set (replayed while
     // the set, its buffers and the context buffers are unchanged), its own
@@ -194,6 +198,10 @@ rp_status rp_create(rp_ctx* out, int device) {
     if ((e = hipMemset(ctx->d_status, 0, sizeof(unsigned int))) != hipSuccess) return cleanup(e, "hipMemset");
     if ((e = hipMalloc(&ctx->table, 64 * sizeof(rpmi::GroupEntry))) != hipSuccess) return cleanup(e, "hipMalloc");
     ctx->table_entries = 64;
+    if ((e = hipMalloc(&ctx->fold_flags, rpmi::kFoldFlags * sizeof(unsigned int))) != hipSuccess)
+        return cleanup(e, "hipMalloc");
+    if ((e = hipMemset(ctx->fold_flags, 0, rpmi::kFoldFlags * sizeof(unsigned int))) != hipSuccess)
+        return cleanup(e, "hipMemset");
     {
         void* p = nullptr;
         if ((e = rpmi::noalloc_scratch_address(&p)) != hipSuccess || !p)
@@ -216,6 +224,7 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->split_ws) (void)hipFree(ctx->split_ws);
     if (ctx->split_counters) (void)hipFree(ctx->split_counters);
     if (ctx->table) (void)hipFree(ctx->table);
+    if (ctx->fold_flags) (void)hipFree(ctx->fold_flags);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
     if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
@@ -484,6 +493,9 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
     rpmi::ProjArgs a = proj_args(ctx, A, r, pk.data, pk.nt_count, Y, ldy, a_scale_exp);
     a.two_acc = two_acc;
     if (algo == RP_ALGO_SPLIT_F16) {
+        a.fold_flags = ctx->fold_flags;
+        a.fold_epoch = ++ctx->fold_epoch;
+        if (a.fold_epoch == 0) a.fold_epoch = ++ctx->fold_epoch;
         if (rpmi::split_fast_ok(a)) {
             const rpmi::SplitPlan plan = rpmi::plan_split_f16(a.m, a.n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
             if (plan.ksplit > 1) {

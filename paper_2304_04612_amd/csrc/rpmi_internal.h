@@ -58,7 +58,15 @@ struct ProjArgs {
     // host-side routing: take the general kernel with two accumulators
     // (eq:shgemm-3 as written), which has no bound on |Omega|
     bool two_acc = false;
+    // folded split of single wide projections: a 256-row block whose folded
+    // split overflowed is marked fold_flags[block mod kFoldFlags] =
+    // fold_epoch, and the general kernel then recomputes the rows of marked
+    // blocks (a block sharing a flag with a marked one is recomputed too,
+    // which changes nothing); fold_epoch is distinct per launch and never 0
+    unsigned int* fold_flags = nullptr;
+    unsigned int fold_epoch = 0;
 };
+constexpr int kFoldFlags = 4096;      // flag table of the folded split (power of two)
 
 // Several split-FP16 projections in one launch (all on the 16-byte path and
 // of one column width: r <= 128 or r > 128).  The problem table lives in

@@ -194,3 +194,36 @@ def test_e4m3_omega_projection(algo):
     ref = a.astype(np.float64) @ val
     bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, val)
     assert np.all(np.abs(y - ref) <= bound)
+
+
+@pytest.mark.parametrize("m,n,r", [(70, 96, 200), (512, 16384, 256)])
+def test_range_on_the_fast_path(m, n, r):
+    """The wide fast kernel's folded split takes |a| < 32; a row block with a
+    larger element is recomputed by the two-accumulator kernel, which keeps
+    the whole FP16 range: 1000 and 65519 give the exact product within the
+    elementwise bound and RP_OK; 65520, -1e30 and NaN give RP_ERR_RANGE, and
+    NaN stays in its own row.  Shapes on the 16-byte path, the second with a
+    contraction split (partial sums reduced by the last workgroup of a tile)."""
+    announce(f"range on the fast path {m}x{n}x{r}")
+    lib = rp()
+    lib.rp_get_device_status(clear=True)
+    rng = np.random.default_rng(23)
+    om = omega.omega_f16(5, 0, n, r)
+    for big in (31.5, 1000.0, 65519.0):
+        a = rng.standard_normal((m, n)).astype(np.float32)
+        a[m // 2, n // 3] = big
+        y = host(lib.rp_project(dev(a), r, seed=5)).astype(np.float64)
+        assert lib.rp_get_device_status(clear=True) == lib.RP_OK, big
+        ref = project.project_f64(a, om)
+        bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, om)
+        assert np.all(np.abs(y - ref) <= bound), big
+    for bad in (65520.0, -1e30):
+        a = np.ones((m, n), np.float32)
+        a[m - 1, n - 1] = bad
+        lib.rp_project(dev(a), r, seed=5)
+        assert lib.rp_get_device_status(clear=True) == lib.RP_ERR_RANGE, bad
+    a = np.ones((m, n), np.float32)
+    a[5, 6] = np.nan
+    y = host(lib.rp_project(dev(a), r, seed=5))
+    assert np.all(np.isnan(y[5])) and np.all(np.isfinite(np.delete(y, 5, axis=0)))
+    assert lib.rp_get_device_status(clear=True) == lib.RP_ERR_RANGE
