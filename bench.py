@@ -197,6 +197,7 @@ def main():
     del a, y, y32, pk16, pk32
     torch.cuda.empty_cache()
     if not args.no_rsvd:
+        out["rsvd_c1"] = c1_leg(rp, synth, torch, dev)
         out["rsvd"] = rsvd_leg(rp, synth, torch, dev)
     if not args.no_batched:
         out["batched_rsvd"] = batched_leg(rp, synth, torch, dev)
@@ -317,6 +318,34 @@ def load_sigma64():
     return np.array(vals), sha
 
 
+def c1_leg(rp, synth, torch, dev):
+    """The small RSVD: A 1024 x 1024 FP32 = U diag(0.9^i) V^T (Haar U, V), k = 32,
+    oversampling 32, no power iteration; the all-FP32 path (FP32 Omega, FP32
+    kernels) and the split-FP16 path.  Wall time per call (median of 20 after
+    3 warm-up calls, inputs resident; the matrix is cache-resident, so this is
+    a latency figure) and the singular-value error against the planted values
+    (for scale: the first discarded singular value is 0.9^33 = 0.031)."""
+    import numpy as np
+    a = torch.from_numpy(synth.np_planted(1024, 1024, synth.sigma_geometric(1024, 0.9),
+                                          np.random.default_rng(101))).to(dev)
+    planted = torch.tensor(synth.sigma_geometric(1024, 0.9)[:32], device=dev)
+    out = {"workload": "rsvd A 1024x1024 FP32 sigma_i=0.9^i, k=32, s=32, q=0"}
+    for omega_type, algo in (("f32", "f32"), ("f16", "split_f16")):
+        walls = []
+        for rep in range(23):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sv, _ = rp.rsvd(a, 32, 32, 0, 201, omega_type, algo)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        walls = sorted(walls[3:])
+        out[algo] = {"wall_s_median": round(walls[len(walls) // 2], 6), "wall_s_min": round(walls[0], 6),
+                     "max_abs_sigma_err_vs_planted": float((sv - planted).abs().max().item()),
+                     "device_status": rp.status_string(rp.rp_get_device_status(clear=True))}
+    log(f"C1 RSVD 1024^2: {out}")
+    return out
+
+
 def rsvd_leg(rp, synth, torch, dev):
     """Full randomized SVD: A 32768 x 32768 FP32 = U diag(sigma) V^T + noise,
     planted rank 512 with sigma_i = 10^(-(i-1)/511), noise N(0, (1e-4)^2);
@@ -400,6 +429,18 @@ def batched_leg(rp, synth, torch, dev):
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_leg(a, y, y32, rows):
     """The FP64 oracle on a row sample, timed on the host cores; its result
     also gives the relative errors of both GPU kernels on that sample."""
@@ -428,6 +469,7 @@ def cpu_leg(a, y, y32, rows):
         "sample": f"{rows} of {M} rows of A x full Omega ({N}x{R}); time = oracle Omega generation "
                   f"({t1 - t0:.2f} s) + FP64 product ({t2 - t1:.2f} s)",
         "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
     errs = {"relerr_split_vs_fp64": e_split, "relerr_fp32_vs_fp64": e_f32,
             "error_ratio_split_over_fp32": e_split / e_f32 if e_f32 > 0 else None,

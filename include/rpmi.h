@@ -69,9 +69,18 @@ typedef enum rp_algo_t {
     RP_ALGO_F32 = 0,          /* plain FP32 GEMM on FP32 matrix cores (baseline form);
                                  an FP16 Omega is widened exactly to FP32 first, as
                                  the paper does for its SGEMM comparison (Sec. 4.4.1) */
-    RP_ALGO_SPLIT_F16 = 1     /* A split into FP16 hi + 2^-11 lo on the fly, two FP16
+    RP_ALGO_SPLIT_F16 = 1,    /* A split into FP16 hi + 2^-11 lo on the fly, two FP16
                                  products with FP32 accumulation (Sec. 4.1); requires
                                  an FP16 Omega                                     */
+    RP_ALGO_TCEC_F16 = 2      /* both operands split (the error-corrected product of
+                                 Sec. 2.3, eq:tcec-5): A as for RP_ALGO_SPLIT_F16, an
+                                 FP32 Omega into hi = RN16(w) and RN16(2^11 (w - hi));
+                                 three FP16 products (hi_A hi_W, lo_A hi_W, hi_A lo_W)
+                                 into one FP32 accumulator: FP32-level accuracy for a
+                                 right operand that is not FP16 (the power scheme's
+                                 A W).  Requires an FP32 Omega with |omega| < 32 and
+                                 A on the 16-byte path (16-byte aligned, s_row,
+                                 k_inner and s_k_outer multiples of 4)          */
 } rp_algo_t;
 
 /*
@@ -145,16 +154,20 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
  *              two column scales of rp_omega_generate_e4m3; the projection
  *              takes Omega8[i][j] / s_j (exact in FP16 for s_j in
  *              [2^-7, 2^15]).  Ignored otherwise (may be NULL).
- *   algo       RP_ALGO_SPLIT_F16 (needs an FP16 or e4m3 Omega) or RP_ALGO_F32.
+ *   algo       RP_ALGO_SPLIT_F16 (needs an FP16 or e4m3 Omega), RP_ALGO_TCEC_F16
+ *              (needs an FP32 Omega and A on the 16-byte path, otherwise
+ *              RP_ERR_UNSUPPORTED) or RP_ALGO_F32.
  *   a_scale_exp  s: the split takes 2^s A instead of A and the epilogue
  *              multiplies by 2^-s (both exact while 2^s A and Y stay inside
  *              the FP32 normal range), so that an A whose magnitudes exceed
  *              the FP16 range (Sec. 4.2) can be brought inside it; 0 = off.
- *              |s| <= 64.  Ignored by RP_ALGO_F32.
+ *              |s| <= 64.  Ignored by RP_ALGO_F32 and RP_ALGO_TCEC_F16.
  * With RP_ALGO_SPLIT_F16 an element of 2^s A that overflows FP16 (finite
  * |2^s a| >= 65520), or a non-finite element, sets RP_ERR_RANGE in the device
  * status word; Y is then unspecified (a NaN element leaves NaN in its own
- * row of Y).  A caller FP16 or e4m3 Omega is scanned on the device: when it
+ * row of Y); the same holds for A with RP_ALGO_TCEC_F16, whose FP32 Omega
+ * records RP_ERR_OMEGA_RANGE when an entry has |omega| >= 32 (the hi products
+ * take 2^11 RN16(omega)) or is not finite.  A caller FP16 or e4m3 Omega is scanned on the device: when it
  * holds an entry with |omega| >= 32 the call takes the kernel with two
  * accumulators (eq:shgemm-3 as written), which has no such bound; the scan
  * is read back once, so such a call synchronises `stream`.
@@ -179,7 +192,9 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r,
  * rp_omega_generate_e4m3()) does.  The split-FP16 algorithm takes FP16
  * fragments (type RP_OMEGA_F16, or RP_OMEGA_E4M3 whose values Omega8 / s_j
  * are exact in FP16); the FP32 algorithm takes FP32 fragments (an FP16 or
- * e4m3 Omega is widened exactly).  col_scale: r floats (device) for a caller
+ * e4m3 Omega is widened exactly); the TCEC algorithm takes an FP32 Omega
+ * (type RP_OMEGA_F32) as FP16 hi fragments followed by FP16 RN16(2^11 (w -
+ * hi)) fragments (|omega| >= 32 records RP_ERR_OMEGA_RANGE).  col_scale: r floats (device) for a caller
  * e4m3 Omega, else ignored.  Packing a caller Omega for the split-FP16
  * algorithm records RP_ERR_OMEGA_RANGE in the device status word if an entry
  * has |omega| >= 32 or is not finite (or a column scale is not a power of two
@@ -219,11 +234,28 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
  * units).  Each call first clears the counters it uses with a kernel.  All
  * calls on one device share the array and it keeps the last call's
  * contents: calls that overlap in time on one device (any contexts, any
- * streams) race and give undefined results.
+ * streams) race and give undefined results.  algo RP_ALGO_F32 or
+ * RP_ALGO_SPLIT_F16 (RP_ALGO_TCEC_F16 returns RP_ERR_INVALID_ARG).
  */
 rp_status rp_project_packed_noalloc(rp_ctx ctx, const rp_desc* A, int64_t r, const void* packed,
                                     rp_algo_t algo, int32_t a_scale_exp, float* Y, int64_t ldy,
                                     void* stream);
+
+/*
+ * Z = A^T Q: the product of Algorithm 1 line 3 (B^T = A^T Q, Q with
+ * orthonormal columns) and of the power scheme's A^T Q, for callers that run
+ * the other steps themselves.  A m x n FP32 row-major (lda >= n), Q m x p
+ * FP32 row-major (ldq >= p), Z n x p FP32 row-major (ldz >= p), all device.
+ * algo RP_ALGO_F32: FP32 matrix cores.  RP_ALGO_TCEC_F16: both operands split
+ * (Sec. 2.3, eq:tcec-5) on FP16 matrix cores; needs n and lda multiples of 4
+ * and a 16-byte aligned A (otherwise RP_ERR_UNSUPPORTED), and records
+ * RP_ERR_OMEGA_RANGE for an entry |q| >= 32 and RP_ERR_RANGE for an A
+ * element with |a| >= 65520 or not finite (Z then unspecified).  The TCEC
+ * form first packs Q into the context workspace (growing it allocates and
+ * synchronises the device).  m == 0 writes Z = 0.
+ */
+rp_status rp_gemm_tn(rp_ctx ctx, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda,
+                     const float* Q, int64_t ldq, rp_algo_t algo, float* Z, int64_t ldz, void* stream);
 
 /*
  * Randomized SVD (Algorithm 1, Sec. 2.2) of the m x n FP32 matrix A (row-major,
@@ -235,9 +267,12 @@ rp_status rp_project_packed_noalloc(rp_ctx ctx, const rp_desc* A, int64_t r, con
  *     Q = QR(Y);  B = Q^T A;  U', S, V' = SVD(B);  U = Q U'[:, :k].
  * Omega is generated from (seed, stream_id 0) in omega_type and the
  * projection runs with `algo` (RP_ALGO_SPLIT_F16 is the paper's method;
- * RP_ALGO_F32 the baseline); A^T Q (power scheme and B) and A W run on this
- * library's FP32 matrix-core kernels, the products with the small factors in
- * FP32 with FP64 accumulation.  Every QR is CholeskyQR2 with the Gram
+ * RP_ALGO_F32 the baseline); A^T Q (power scheme and B) and A W (power
+ * scheme) run on the TCEC products (RP_ALGO_TCEC_F16, rp_gemm_tn) when algo
+ * is RP_ALGO_SPLIT_F16, a_scale_exp is 0 and A is on the 16-byte path (n and
+ * lda multiples of 4, 16-byte aligned), else on this library's FP32
+ * matrix-core kernels; the
+ * products with the small factors in FP32 with FP64 accumulation.  Every QR is CholeskyQR2 with the Gram
  * matrix, Cholesky factor and triangular inverse in FP64; the SVD of B is
  * taken as B^T = Q_B R_B (CholeskyQR2) followed by a one-sided Jacobi SVD of
  * R_B^T in FP64 (at most 16 sweeps).  Outside stream capture the call reads a
@@ -385,8 +420,10 @@ rp_status rp_split_f16(rp_ctx ctx, const float* x, int64_t count,
 /*
  * Synchronise `stream`, then return in *out the device status word of the
  * context as a status code (RP_OK if nothing was recorded; otherwise the
- * first recorded condition in the order RP_ERR_RANGE, RP_ERR_NOT_SPD,
- * RP_ERR_NOT_CONVERGED).  If `clear` is non-zero the word is reset.
+ * first recorded condition in the order RP_ERR_OMEGA_RANGE, RP_ERR_RANGE,
+ * RP_ERR_NOT_SPD, RP_ERR_NOT_CONVERGED; an Omega outside its range makes the
+ * products non-finite as well, so it is reported as the cause).  If `clear`
+ * is non-zero the word is reset.
  */
 rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* out);
 

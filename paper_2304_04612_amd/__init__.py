@@ -27,9 +27,10 @@ RP_OMEGA_F16 = 1
 RP_OMEGA_E4M3 = 2
 RP_ALGO_F32 = 0
 RP_ALGO_SPLIT_F16 = 1
+RP_ALGO_TCEC_F16 = 2
 
 OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16, "e4m3": RP_OMEGA_E4M3}
-ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16}
+ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16, "tcec_f16": RP_ALGO_TCEC_F16}
 
 
 class RpError(RuntimeError):
@@ -79,6 +80,7 @@ def lib():
         "rp_omega_pack": [vp, u64, u32, vp, i64, vp, i32, i64, i64, i32, vp, vp],
         "rp_project_packed": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, i32, vp, i64, vp],
         "rp_project_packed_noalloc": [vp, ctypes.POINTER(rp_desc), i64, vp, i32, i32, vp, i64, vp],
+        "rp_gemm_tn": [vp, i64, i64, i64, vp, i64, vp, i64, i32, vp, i64, vp],
         "rp_get_device_status": [vp, vp, i32, ctypes.POINTER(i32)],
         "rsvd": [vp, i64, i64, vp, i64, i64, i64, i32, u64, i32, i32, i32, vp, i64, vp, vp, i64, vp,
                  ctypes.c_size_t, vp],
@@ -243,6 +245,21 @@ def rp_project_packed_noalloc(a, r, packed, y, algo="split_f16", desc=None, a_sc
     _check(ctx.handle, lib().rp_project_packed_noalloc(ctx.handle, ctypes.byref(d), r, _ptr(packed), ALGOS[algo],
                                                        int(a_scale_exp), _ptr(y), ldy, _stream()))
     return y
+
+
+def rp_gemm_tn(a, q, algo="tcec_f16", z=None, ctx=None):
+    """Z = A^T Q for float32 CUDA tensors a (m x n) and q (m x p), row-major
+    with unit column stride; returns z (n x p)."""
+    import torch
+    ctx = ctx or default_context()
+    m, n = a.shape
+    p = q.shape[1]
+    if z is None:
+        z = torch.empty((n, p), dtype=torch.float32, device=a.device)
+    _check(ctx.handle, lib().rp_gemm_tn(ctx.handle, m, n, p, _ptr(a), a.stride(0) if a.numel() else max(n, 1),
+                                        _ptr(q), q.stride(0) if q.numel() else max(p, 1), ALGOS[algo], _ptr(z),
+                                        z.stride(0) if z.numel() else max(p, 1), _stream()))
+    return z
 
 
 def rp_split_f16(x, ctx=None):

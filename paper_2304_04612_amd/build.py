@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librpmi.so")
 
-HIP_SOURCES = ["project_wide.hip", "project_narrow.hip", "project.hip", "omega.hip", "linalg.hip", "group_linalg.hip", "noalloc.hip",
+HIP_SOURCES = ["project_wide.hip", "project_narrow.hip", "project.hip", "omega.hip", "linalg.hip", "group_linalg.hip", "noalloc.hip", "tn_tcec.hip",
                "rpmi_api.cpp"]
 HOST_SOURCES = ["lattice_host.cpp"]
 ARCH = "gfx950"

@@ -180,8 +180,14 @@ __global__ __launch_bounds__(1024) void svd_sigma_group_kernel(const SvdJob* __r
     }
     __syncthreads();
     for (int j = tid; j < n; j += blockDim.x) {
+        // rank by (key, index) with NaN keyed below every sigma (>= 0), so that
+        // the ranks are a permutation of 0 .. n-1 whatever W holds
+        const double kj = s[j] == s[j] ? s[j] : -1.0;
         int rank = 0;
-        for (int i = 0; i < n; ++i) rank += (s[i] > s[j]) || (s[i] == s[j] && i < j);
+        for (int i = 0; i < n; ++i) {
+            const double ki = s[i] == s[i] ? s[i] : -1.0;
+            rank += (ki > kj) || (ki == kj && i < j);
+        }
         J.sig[rank] = s[j];
         J.order[rank] = j;
         if (rank < J.ncols) J.S[rank] = s[j];
@@ -195,7 +201,8 @@ __global__ void svd_gather_group_kernel(const SvdJob* __restrict__ jobs) {
     const int64_t total = (int64_t)J.n * J.ncols;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / J.ncols), cidx = (int)(e % J.ncols);
-        const int src = J.order[cidx];
+        int src = J.order[cidx];
+        src = src < 0 ? 0 : (src >= J.n ? J.n - 1 : src);   // a permutation by construction; never index past W
         const double sg = J.sig[cidx];
         J.Ur[e] = sg > 0.0 ? J.W[(int64_t)r * J.n + src] / sg : 0.0;
         J.Vr[e] = J.V[(int64_t)r * J.n + src];

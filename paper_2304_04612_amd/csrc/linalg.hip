@@ -30,6 +30,7 @@ namespace {
 constexpr int GT = kG64Tile;   // output tile
 constexpr int GK = kG64K;     // contraction slice
 constexpr int NB = 64;      // block size of the factorizations
+constexpr int kJacobiWavePairs = 2048;   // pairs per round from which a wave per pair is faster
 
 template <class T>
 __device__ __forceinline__ double ld(const T* p) { return (double)*p; }
@@ -162,6 +163,22 @@ __global__ void zero_upper_kernel(double* A, int64_t lda, int64_t p) {
 
 
 // G = sum over z of the split partials, in the fixed order z = 0, 1, ...
+// One part z of G = Y^T Y (p x p, FP64) over contraction rows [z Kc, (z+1) Kc):
+// block x enumerates the tiles (ti, tj), ti <= tj, of the upper triangle; each
+// tile is written with its mirror.  out + z p^2 receives the part.
+template <class T>
+__global__ __launch_bounds__(256) void gram_sym_kernel(int64_t p, int64_t K, int64_t Kc, const T* Y, int64_t ldy,
+                                                       double* out) {
+    const int64_t nt = (p + GT - 1) / GT;
+    int64_t t = blockIdx.x, ti = 0;
+    while (t >= nt - ti) { t -= nt - ti; ++ti; }
+    const int64_t tj = ti + t;
+    const int64_t z = blockIdx.y, k0 = z * Kc;
+    const int64_t kz = K - k0 < Kc ? K - k0 : Kc;
+    const T* a = Y + k0 * ldy;
+    gemm64_tile<T, T, double, true>(p, p, kz, 1.0, a, 1, ldy, a, ldy, 1, 0.0, out + z * p * p, p, 1, ti * GT, tj * GT);
+}
+
 __global__ void sum_partials_kernel(const double* __restrict__ part, int64_t count, int nsplit, double* __restrict__ G) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
         double acc = part[e];
@@ -260,13 +277,28 @@ __global__ void jacobi_prep_kernel(const JacobiProb* tab) {
     if (blockIdx.x == 0 && threadIdx.x < 4) P.flags[threadIdx.x] = 0;
 }
 
-// One round: one wave per column pair (four pairs per workgroup), so the
-// three dot products of the pair's 2x2 Gram are reduced within the wave
-// (lane-strided partial sums, then a butterfly) with no workgroup barrier.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One round of the parallel one-sided Jacobi SVD.  WAVE = false: one
+// workgroup per column pair, the pair's three dot products reduced over 256
+// threads (about 2.5 rows per thread at n = 640, which keeps a round
+// latency-short: 5.8 us at n = 640 against 10.3 us for one wave per pair).
+// WAVE = true: one wave per pair, four pairs per workgroup, reduced within
+// the wave with no workgroup barrier (faster when a round has thousands of
+// pairs, as in the batched RSVD).
+template <bool WAVE>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab, int count, int total_pairs,
                                                            int round, int sweep, double tol) {
-    const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int STRIDE = WAVE ? 64 : 256;
+    const int t0 = WAVE ? (threadIdx.x & 63) : threadIdx.x;
+    const int b = WAVE ? blockIdx.x * 4 + (threadIdx.x >> 6) : blockIdx.x;
     if (b >= total_pairs) return;
     int lo = 0, hi = count - 1;
     while (lo < hi) {
@@ -287,14 +319,22 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     double* wa = P.W + (int64_t)a * n;
     double* wc = P.W + (int64_t)c * n;
     double al = 0.0, be = 0.0, ga = 0.0;
-    for (int r = lane; r < n; r += 64) {
+    for (int r = t0; r < n; r += STRIDE) {
         const double x = wa[r], y = wc[r];
         al += x * x; be += y * y; ga += x * y;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        al += __shfl_xor(al, off, 64);
-        be += __shfl_xor(be, off, 64);
-        ga += __shfl_xor(ga, off, 64);
+    if constexpr (WAVE) {
+        // butterfly: every lane ends with the same bits, so the lanes agree
+        for (int off = 32; off > 0; off >>= 1) {
+            al += __shfl_xor(al, off, 64);
+            be += __shfl_xor(be, off, 64);
+            ga += __shfl_xor(ga, off, 64);
+        }
+    } else {
+        __shared__ double red[3][4];
+        al = block_sum256(al, red[0]);
+        be = block_sum256(be, red[1]);
+        ga = block_sum256(ga, red[2]);
     }
     if (!(fabs(ga) > tol * sqrt(al * be)) || ga == 0.0) return;
     // the rotation that zeroes the off-diagonal of the pair's 2x2 Gram
@@ -303,7 +343,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
     double* va = P.V + (int64_t)a * n;
     double* vc = P.V + (int64_t)c * n;
-    for (int r = lane; r < n; r += 64) {
+    for (int r = t0; r < n; r += STRIDE) {
         const double x = wa[r], y = wc[r];
         wa[r] = cs * x - sn * y;
         wc[r] = sn * x + cs * y;
@@ -311,7 +351,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
         va[r] = cs * vx - sn * vy;
         vc[r] = sn * vx + cs * vy;
     }
-    if (lane == 0) P.flags[1 + (sweep & 1)] = 1;
+    if (t0 == 0) P.flags[1 + (sweep & 1)] = 1;
 }
 
 __global__ void set_jacobi_prob_kernel(JacobiProb* dst, JacobiProb v) {
@@ -359,8 +399,14 @@ __global__ __launch_bounds__(1024) void svd_finish_kernel(const double* W, int n
     }
     __syncthreads();
     for (int j = tid; j < n; j += blockDim.x) {
+        // rank by (key, index) with NaN keyed below every sigma (>= 0), so that
+        // the ranks are a permutation of 0 .. n-1 whatever W holds
+        const double kj = s[j] == s[j] ? s[j] : -1.0;
         int rank = 0;
-        for (int i = 0; i < n; ++i) rank += (s[i] > s[j]) || (s[i] == s[j] && i < j);
+        for (int i = 0; i < n; ++i) {
+            const double ki = s[i] == s[i] ? s[i] : -1.0;
+            rank += (ki > kj) || (ki == kj && i < j);
+        }
         sig_sorted[rank] = s[j];
         order[rank] = j;
     }
@@ -373,7 +419,8 @@ __global__ void svd_gather_kernel(const double* W, const double* Vin, int n, con
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)n * ncols;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / ncols), cidx = (int)(e % ncols);
-        const int src = order[cidx];
+        int src = order[cidx];
+        src = src < 0 ? 0 : (src >= n ? n - 1 : src);   // a permutation by construction; never index past W
         const double sg = sig[cidx];
         Ur[e] = sg > 0.0 ? W[(int64_t)r * n + src] / sg : 0.0;
         Vr[e] = Vin[(int64_t)r * n + src];
@@ -511,22 +558,18 @@ template <class T>
 hipError_t gram_acc64(int64_t p, int64_t K, const T* Y, int64_t ldy, double* G, double* partial, int max_split,
                       hipStream_t s) {
     if (p <= 0) return hipSuccess;
-    const int64_t tiles = ((p + GT - 1) / GT) * ((p + GT - 1) / GT);
-    int64_t S = 512 / tiles;                         // enough workgroups for the chip
+    const int64_t nt = (p + GT - 1) / GT, tri = nt * (nt + 1) / 2;
+    int64_t S = (1024 + tri - 1) / tri;              // about 4 workgroups per compute unit
     S = S > max_split ? max_split : S;
     S = S > K / 512 ? K / 512 : S;                   // at least 512 contraction rows per part
-    if (S <= 1 || !partial)
-        return gemm_acc64<T, T, double>(p, p, K, 1.0, Y, 1, ldy, Y, ldy, 1, 0.0, G, p, 1, s);
-    const int64_t Kc = ((K + S - 1) / S + GK - 1) / GK * GK;
-    const int64_t parts = (K + Kc - 1) / Kc;         // the first parts - 1 are full
-    const int64_t last = K - (parts - 1) * Kc;
-    hipError_t e = gemm_acc64_batched<T, T, double>(p, p, Kc, 1.0, Y, 1, ldy, Kc * ldy, Y, ldy, 1, Kc * ldy, 0.0,
-                                                    partial, p, 1, p * p, parts - 1, s);
-    if (e != hipSuccess) return e;
-    e = gemm_acc64<T, T, double>(p, p, last, 1.0, Y + (parts - 1) * Kc * ldy, 1, ldy, Y + (parts - 1) * Kc * ldy, ldy,
-                                 1, 0.0, partial + (parts - 1) * p * p, p, 1, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(grid1d(p * p)), dim3(256), 0, s, partial, p * p, (int)parts, G);
+    if (S < 1 || !partial) S = 1;
+    const int64_t Kc = S == 1 ? K : ((K + S - 1) / S + GK - 1) / GK * GK;
+    const int64_t parts = S == 1 ? 1 : (K + Kc - 1) / Kc;
+    if (parts > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gram_sym_kernel<T>), dim3((unsigned)tri, (unsigned)parts), dim3(256), 0, s, p, K, Kc, Y, ldy,
+                       parts == 1 ? G : partial);
+    if (parts > 1)
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(grid1d(p * p)), dim3(256), 0, s, partial, p * p, (int)parts, G);
     return hipGetLastError();
 }
 
@@ -565,8 +608,12 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
     const int max_m = max_n + (max_n & 1);
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int round = 0; round < max_m - 1; ++round) {
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)((total_pairs + 3) / 4)), dim3(256), 0, s, tab,
-                               count, total_pairs, round, sweep, tol);
+            if (total_pairs >= kJacobiWavePairs)
+                hipLaunchKernelGGL(jacobi_round_kernel<true>, dim3((unsigned)((total_pairs + 3) / 4)), dim3(256), 0, s,
+                                   tab, count, total_pairs, round, sweep, tol);
+            else
+                hipLaunchKernelGGL(jacobi_round_kernel<false>, dim3((unsigned)total_pairs), dim3(256), 0, s, tab,
+                                   count, total_pairs, round, sweep, tol);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, tab,

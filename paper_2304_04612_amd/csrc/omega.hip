@@ -220,6 +220,42 @@ __global__ void pack_omega_kernel(const void* src, const float* col_scale, int64
     if (status && bad_scale) atomicOr(status, kStatusOmegaRange);
 }
 
+// TCEC packing of an FP32 right operand (eq:tcec-5): hi = RN16(w) and
+// lo = RN16(2^11 (w - hi)) in fragment order, the lo fragments after all hi
+// fragments.  w - hi is exact in FP32.  One thread per (fragment, lane).
+__global__ void pack_omega_tcec_kernel(const float* src, int64_t n, int64_t r, int64_t ldo, uint16_t* dst,
+                                       int64_t kb_count, int64_t nt_count, unsigned int* flag,
+                                       unsigned int flag_bit) {
+    const int64_t total = kb_count * nt_count * 64;
+    bool bad = false;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(q & 63), g = lane >> 4, c = lane & 15;
+        const int64_t frag = q >> 6;
+        const int64_t kb = frag / nt_count, nt = frag - kb * nt_count;
+        const int64_t col = nt * kNTile + c;
+        uint16_t hv[8], lv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t row = kb * kKBlock + frag_slot(g, e);
+            const float w = row < n && col < r ? src[row * ldo + col] : 0.0f;
+            const _Float16 h = (_Float16)w;
+            const _Float16 l = (_Float16)((w - (float)h) * 2048.0f);
+            hv[e] = __builtin_bit_cast(uint16_t, h);
+            lv[e] = __builtin_bit_cast(uint16_t, l);
+            bad |= (hv[e] & 0x7FFFu) >= 0x5000u;      // |hi| >= 32, inf or NaN
+        }
+        uint4 ph, pl;
+        ph.x = hv[0] | ((uint32_t)hv[1] << 16); ph.y = hv[2] | ((uint32_t)hv[3] << 16);
+        ph.z = hv[4] | ((uint32_t)hv[5] << 16); ph.w = hv[6] | ((uint32_t)hv[7] << 16);
+        pl.x = lv[0] | ((uint32_t)lv[1] << 16); pl.y = lv[2] | ((uint32_t)lv[3] << 16);
+        pl.z = lv[4] | ((uint32_t)lv[5] << 16); pl.w = lv[6] | ((uint32_t)lv[7] << 16);
+        *reinterpret_cast<uint4*>(dst + q * 8) = ph;
+        *reinterpret_cast<uint4*>(dst + (total + q) * 8) = pl;
+    }
+    if (flag && bad) atomicOr(flag, flag_bit);
+}
+
 int grid_for(int64_t total, int block) {
     int64_t g = (total + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -336,6 +372,16 @@ hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL(omega_packed_f16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, seed, stream_id, n, r,
                        static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_omega_tcec(const float* src, int64_t n, int64_t r, int64_t ldo, const PackedOmega& dst,
+                                  unsigned int* flag, unsigned int flag_bit, hipStream_t s) {
+    const int64_t total = dst.kb_count * dst.nt_count * 64;
+    if (total == 0) return hipSuccess;
+    const int block = 256, grid = grid_for(total, block);
+    hipLaunchKernelGGL(pack_omega_tcec_kernel, dim3(grid), dim3(block), 0, s, src, n, r, ldo,
+                       static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count, flag, flag_bit);
     return hipGetLastError();
 }
 

@@ -36,6 +36,11 @@
 //    tiles; the contraction split that fills the chip gives every XCD a
 //    contiguous run of block ids (block ids are dealt to the XCDs round
 //    robin), so the workgroups of one XCD share one slice of Omega in its L2.
+//  * With a contraction split the single (folded) form only writes its
+//    partial sums and a second kernel adds them.  Adding them in the last
+//    workgroup to arrive needs a device-scope release per workgroup, which on
+//    this chip writes back the XCD's L2; at 16384 x 16384 x 256 that epilogue
+//    took 40-130 us after main loops that all ended near 210 us.
 #pragma once
 #include "proj_common.h"
 
@@ -103,12 +108,16 @@ __device__ __forceinline__ void split8_fold(const floatx4& a0, const floatx4& a1
     y = __builtin_bit_cast(half8, u32x4{y0, y1, y2, y3});
 }
 
-template <class C, bool FOLD>
+template <class C, bool FOLD, bool TCEC = false>
 __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t bm, const int64_t bn, const int kz,
                                                const int64_t tiles_n) {
+    static_assert(!(FOLD && TCEC), "the TCEC products take the exact split");
     constexpr int TM = C::TM, TN = C::TN, S = C::S;
+    constexpr int OPS = C::A_OPS + (TCEC ? 2 : 1) * C::O_OPS;   // memory instructions per step
+    static_assert((S - 2) * OPS < 64, "vmcnt range");
     __shared__ floatx4 sa0[C::A_F4], sa1[C::A_F4], sa2[C::A_F4];
     __shared__ half8 so0[C::O_H8], so1[C::O_H8], so2[C::O_H8];
+    __shared__ half8 sd0[TCEC ? C::O_H8 : 1], sd1[TCEC ? C::O_H8 : 1], sd2[TCEC ? C::O_H8 : 1];
     auto sa_at = [&](auto slot_c) RPMI_INLINE -> floatx4* {
         constexpr int k = decltype(slot_c)::value;
         if constexpr (k == 0) return sa0;
@@ -120,6 +129,12 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
         if constexpr (k == 0) return so0;
         else if constexpr (k == 1) return so1;
         else return so2;
+    };
+    auto sd_at = [&](auto slot_c) RPMI_INLINE -> half8* {
+        constexpr int k = decltype(slot_c)::value;
+        if constexpr (k == 0) return sd0;
+        else if constexpr (k == 1) return sd1;
+        else return sd2;
     };
 
     const int tid = threadIdx.x;
@@ -166,6 +181,8 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
     const char* obase = static_cast<const char*>(p.omega) +
                         ((bn * TN + wave * C::O_OPS) * 64 + lane) * (int64_t)sizeof(half8);
     const int64_t ostep = p.nt_count * 64 * (int64_t)sizeof(half8);
+    const char* obase_lo = TCEC ? static_cast<const char*>(p.omega_lo) + (obase - static_cast<const char*>(p.omega))
+                                : nullptr;
     const float kfold = 2048.0f * p.a_scale;      // exact: a power of two
 
     floatx4 acc[TM][TN];
@@ -187,6 +204,14 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
         for (int i = 0; i < C::O_OPS; ++i)
             __builtin_amdgcn_global_load_lds(RPMI_GLB(osrc + i * 1024), RPMI_LDS(so + (wave * C::O_OPS + i) * 64), 16,
                                              0, 0);
+        if constexpr (TCEC) {
+            half8* sd = sd_at(slot_c);
+            const char* dsrc = obase_lo + jcur * ostep;
+#pragma unroll
+            for (int i = 0; i < C::O_OPS; ++i)
+                __builtin_amdgcn_global_load_lds(RPMI_GLB(dsrc + i * 1024), RPMI_LDS(sd + (wave * C::O_OPS + i) * 64),
+                                                 16, 0, 0);
+        }
         const bool last = jcur + 1 == je;
         iin += C::BK;
         const bool wrap = iin >= p.k_inner;
@@ -201,11 +226,16 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
     // fragments in groups of 4 (the next group's LDS reads in flight while
     // the current group's 16 MFMAs run; per group the hi products, then the
     // lo products, so that two updates of one accumulator are 8 apart)
+    // (TCEC: a third set, hi_A lo_W, after the lo products)
     constexpr int FG = 4, NG = TN / FG;
-    auto compute = [&](const floatx4 (&a)[TM][2], const half8* so) RPMI_INLINE {
-        half8 bq[2][FG];
+    auto compute = [&](const floatx4 (&a)[TM][2], const half8* so, const half8* sd) RPMI_INLINE {
+        half8 bq[2][FG], bd[2][TCEC ? FG : 1];
 #pragma unroll
         for (int f = 0; f < FG; ++f) bq[0][f] = so[f * 64 + lane];
+        if constexpr (TCEC) {
+#pragma unroll
+            for (int f = 0; f < FG; ++f) bd[0][f] = sd[f * 64 + lane];
+        }
         half8 hi[TM], lo[TM];
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm) {
@@ -217,6 +247,10 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
             if (q + 1 < NG) {
 #pragma unroll
                 for (int f = 0; f < FG; ++f) bq[(q + 1) & 1][f] = so[((q + 1) * FG + f) * 64 + lane];
+                if constexpr (TCEC) {
+#pragma unroll
+                    for (int f = 0; f < FG; ++f) bd[(q + 1) & 1][f] = sd[((q + 1) * FG + f) * 64 + lane];
+                }
             }
             half8 bh[FG];
 #pragma unroll
@@ -233,19 +267,27 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
                 for (int tm = 0; tm < TM; ++tm)
                     acc[tm][q * FG + f] =
                         __builtin_amdgcn_mfma_f32_16x16x32_f16(lo[tm], bq[q & 1][f], acc[tm][q * FG + f], 0, 0, 0);
+            if constexpr (TCEC) {
+#pragma unroll
+                for (int f = 0; f < FG; ++f)
+#pragma unroll
+                    for (int tm = 0; tm < TM; ++tm)
+                        acc[tm][q * FG + f] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_f16(hi[tm], bd[q & 1][f], acc[tm][q * FG + f], 0, 0, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     };
 
     auto step = [&](auto slot_c) RPMI_INLINE {
         constexpr int s = decltype(slot_c)::value;
-        wait_vm_barrier<(S - 2) * C::OPS>();
+        wait_vm_barrier<(S - 2) * OPS>();
         issue(IntC<(s + S - 1) % S>{});
         const floatx4* sa = sa_at(slot_c);
         floatx4 a[TM][2];
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm) { a[tm][0] = aread(sa, tm, 0); a[tm][1] = aread(sa, tm, 1); }
-        compute(a, so_at(slot_c));
+        compute(a, so_at(slot_c), sd_at(slot_c));
     };
 
     if (nsteps > 0) {
@@ -281,9 +323,11 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
         for (int i = 0; i < C::O_OPS; ++i) {
             const int f = wave * C::O_OPS + i;
             so0[f * 64 + lane] = om[(nfull * p.nt_count + bn * TN + f) * 64 + lane];
+            if constexpr (TCEC)
+                sd0[f * 64 + lane] = static_cast<const half8*>(p.omega_lo)[(nfull * p.nt_count + bn * TN + f) * 64 + lane];
         }
         __syncthreads();
-        compute(a, so0);
+        compute(a, so0, sd0);
     }
 
     // Range: a non-finite accumulator means an element whose x (folded) or hi
@@ -297,8 +341,7 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
     const float yscale = FOLD ? 0x1p-11f * p.y_scale : 0x1p-11f;
 
     if (p.ksplit > 1) {
-        // partial sums in lane order (16 bytes per lane per fragment), then the
-        // last workgroup of the tile adds all ksplit partials in order z = 0, 1, ...
+        // partial sums in lane order (16 bytes per lane per fragment)
         const int64_t tile = bm * tiles_n + bn;
         constexpr int TILE_F4 = TM * TN * C::THREADS;
         floatx4* mine = reinterpret_cast<floatx4*>(p.partial) + (tile * p.ksplit + kz) * TILE_F4;
@@ -306,6 +349,11 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
         for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
             for (int j = 0; j < TN; ++j) mine[(tm * TN + j) * C::THREADS + tid] = acc[tm][j];
+        // single forms (folded, TCEC): a second kernel (split_lds_reduce_kernel)
+        // adds the partials, so no workgroup waits on a device-scope release
+        // (an L2 write-back on this chip); grouped form: the last workgroup of
+        // the tile to arrive adds all ksplit partials in order z = 0, 1, ...
+        if constexpr (FOLD || TCEC) return;
         __threadfence();
         __shared__ unsigned int arrival;
         __syncthreads();
@@ -371,6 +419,44 @@ __global__ __launch_bounds__(C::THREADS, 1) void project_split_lds_single_kernel
     const int kz = (int)(b / per_k);
     const int64_t rest = b - kz * per_k;
     split_lds_body<C, true>(p, rest / tn, rest % tn, kz, tn);
+}
+
+// TCEC products (eq:tcec-5, both operands split): 128-column tiles, so that
+// the three stages hold A and both Omega arrays (3 x 48 KiB).
+using TcecCfg = LdsCfg<8, 2, 8, 3>;
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS, 1) void project_tcec_lds_kernel(ProjArgs p) {
+    const int64_t tn = (p.r + C::BN - 1) / C::BN, tm = (p.m + C::BM - 1) / C::BM;
+    const int64_t b = xcd_dense_block(blockIdx.x, gridDim.x), per_k = tm * tn;
+    const int kz = (int)(b / per_k);
+    const int64_t rest = b - kz * per_k;
+    split_lds_body<C, false, true>(p, rest / tn, rest % tn, kz, tn);
+}
+
+// Second pass of a folded or TCEC projection with a contraction split: Y = 2^-11 y_scale
+// sum_z partial_z, summed in the fixed order z = 0, 1, ... (the result does not
+// depend on the order in which the first pass's workgroups ran).  One block
+// per (tile, fragment); thread t of the block holds what thread t of the
+// first pass's workgroup held for that fragment.
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void split_lds_reduce_kernel(ProjArgs p) {
+    constexpr int TM = C::TM, TN = C::TN, NF = TM * TN, TILE_F4 = NF * C::THREADS;
+    const int64_t tn = (p.r + C::BN - 1) / C::BN;
+    const int64_t tile = blockIdx.x / NF;
+    const int f = (int)(blockIdx.x % NF), tm = f / TN, j = f % TN;
+    const int64_t bm = tile / tn, bn = tile % tn;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+    const floatx4* src = reinterpret_cast<const floatx4*>(p.partial) + tile * p.ksplit * TILE_F4 + f * C::THREADS + tid;
+    floatx4 sum = __builtin_nontemporal_load(src);
+    for (int z = 1; z < p.ksplit; ++z) sum += __builtin_nontemporal_load(src + (int64_t)z * TILE_F4);
+    const float yscale = 0x1p-11f * p.y_scale;
+    const int64_t col = bn * C::BN + j * 16 + c;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t row = bm * C::BM + (wave * TM + tm) * 16 + 4 * g + e;
+        if (row < p.m && col < p.r) p.Y[row * p.ldy + col] = sum[e] * yscale;
+    }
 }
 
 }  // namespace

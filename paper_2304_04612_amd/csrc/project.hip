@@ -306,6 +306,22 @@ SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
 int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
 int64_t split_group_tile_n(int64_t r) { return r <= 128 ? DmaTile128::BN : DmaTile::BN; }
 
+int64_t tcec_col_block() { return TcecCfg::BN; }
+SplitPlan plan_tcec(int64_t m, int64_t n, int64_t r, int num_cus) { return plan_for<TcecCfg>(m, n, r, num_cus); }
+
+hipError_t launch_project_tcec(const ProjArgs& a, hipStream_t s) {
+    using C = TcecCfg;
+    if (!split_fast_ok(a) || !a.omega_lo) return hipErrorInvalidValue;
+    const int64_t tiles = ((a.m + C::BM - 1) / C::BM) * ((a.r + C::BN - 1) / C::BN);
+    if (tiles <= 0) return hipSuccess;
+    const int64_t blocks = tiles * (a.ksplit > 1 ? a.ksplit : 1);
+    hipLaunchKernelGGL((project_tcec_lds_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    if (a.ksplit > 1)
+        hipLaunchKernelGGL((split_lds_reduce_kernel<C>), dim3((unsigned)(tiles * C::TM * C::TN)), dim3(C::THREADS), 0,
+                           s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
                                             hipStream_t s, const GroupEntry* one) {
     return narrow ? launch_split_group_narrow(table, count, blocks, one, s)

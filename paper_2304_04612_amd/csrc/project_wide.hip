@@ -9,9 +9,15 @@ hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t b
                                    hipStream_t s) {
     if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
     using C = WideCfg;
-    if (one)
+    if (one) {
         hipLaunchKernelGGL((project_split_lds_single_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                            one->p);
+        if (one->p.ksplit > 1) {
+            const int64_t tiles = one->tiles_m * one->tiles_n;
+            hipLaunchKernelGGL((split_lds_reduce_kernel<C>), dim3((unsigned)(tiles * C::TM * C::TN)), dim3(C::THREADS),
+                               0, s, one->p);
+        }
+    }
     else
         hipLaunchKernelGGL((project_split_lds_grouped_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                            table, count);

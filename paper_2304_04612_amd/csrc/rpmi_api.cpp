@@ -303,7 +303,9 @@ bool proj_layout_ok(rp_ctx ctx, const rp_desc* A, rp_status* st) {
 
 rpmi::PackedOmega packed_geometry(int64_t n, int64_t r, rp_algo_t algo, void* data) {
     rpmi::PackedOmega pk;
-    const int64_t col_block = algo == RP_ALGO_SPLIT_F16 ? rpmi::split_f16_col_block(r) : rpmi::f32_col_block();
+    const int64_t col_block = algo == RP_ALGO_SPLIT_F16  ? rpmi::split_f16_col_block(r)
+                            : algo == RP_ALGO_TCEC_F16 ? rpmi::tcec_col_block()
+                                                       : rpmi::f32_col_block();
     pk.kb_count = round_up(n, rpmi::proj_k_block()) / rpmi::kKBlock;
     pk.nt_count = round_up(r, col_block) / rpmi::kNTile;
     pk.data = data;
@@ -311,6 +313,7 @@ rpmi::PackedOmega packed_geometry(int64_t n, int64_t r, rp_algo_t algo, void* da
 }
 
 size_t packed_bytes(const rpmi::PackedOmega& pk, rp_algo_t algo) {
+    // FP16 fragments; FP32 fragments; TCEC: FP16 hi and lo fragments
     return (size_t)pk.kb_count * pk.nt_count * 64 * 8 * (algo == RP_ALGO_SPLIT_F16 ? 2 : 4);
 }
 
@@ -319,12 +322,16 @@ bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)type);
         return false;
     }
-    if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16) {
+    if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16 && algo != RP_ALGO_TCEC_F16) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "unknown algorithm %d", (int)algo);
         return false;
     }
     if (algo == RP_ALGO_SPLIT_F16 && type == RP_OMEGA_F32) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "the split-FP16 projection needs an FP16 or e4m3 Omega");
+        return false;
+    }
+    if (algo == RP_ALGO_TCEC_F16 && type != RP_OMEGA_F32) {
+        *st = fail(ctx, RP_ERR_INVALID_ARG, "the TCEC products need an FP32 Omega");
         return false;
     }
     return true;
@@ -334,6 +341,7 @@ bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
 size_t raw_bytes(rp_omega_t type, rp_algo_t algo, int64_t n, int64_t r) {
     if (type == RP_OMEGA_E4M3) return (size_t)n * r * 6 + (((size_t)r * 4 + 255) & ~size_t(255)) + 256;
     if (algo == RP_ALGO_F32) return (size_t)n * r * (type == RP_OMEGA_F32 ? 4 : 2);
+    if (algo == RP_ALGO_TCEC_F16) return (size_t)n * r * 4;
     return 0;
 }
 
@@ -347,6 +355,19 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
                       const rpmi::PackedOmega& pk, void* scratch, hipStream_t s, unsigned int* flag = nullptr,
                       unsigned int flag_bit = 0) {
     const bool dst_f32 = algo == RP_ALGO_F32;
+    if (algo == RP_ALGO_TCEC_F16) {
+        // FP32 Omega (the caller's, or generated row-major into scratch), then
+        // its hi and lo fragments; entries with |omega| >= 32 are reported
+        const float* w = static_cast<const float*>(omega);
+        int64_t ld = ldo;
+        if (!w) {
+            RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, true, scratch, r, s));
+            w = static_cast<const float*>(scratch);
+            ld = r;
+        }
+        RP_HIP(ctx, rpmi::launch_pack_omega_tcec(w, n, r, ld, pk, ctx->d_status, rpmi::kStatusOmegaRange, s));
+        return RP_OK;
+    }
     if (omega) {
         const rpmi::OmegaSrc src = type == RP_OMEGA_F32 ? rpmi::OmegaSrc::F32
                                  : type == RP_OMEGA_F16 ? rpmi::OmegaSrc::F16 : rpmi::OmegaSrc::E4M3;
@@ -492,6 +513,28 @@ rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi:
                             bool two_acc = false, const SplitBuffers* sb = nullptr) {
     rpmi::ProjArgs a = proj_args(ctx, A, r, pk.data, pk.nt_count, Y, ldy, a_scale_exp);
     a.two_acc = two_acc;
+    if (algo == RP_ALGO_TCEC_F16) {
+        a.a_scale = a.y_scale = 1.0f;
+        if (!rpmi::split_fast_ok(a))
+            return fail(ctx, RP_ERR_UNSUPPORTED, "the TCEC products need A on the 16-byte path (16-byte aligned, "
+                                                 "row and run strides multiples of 4)");
+        a.omega_lo = static_cast<const char*>(pk.data) + (size_t)pk.kb_count * pk.nt_count * 64 * 8 * 2;
+        const rpmi::SplitPlan plan = rpmi::plan_tcec(a.m, a.n, r, ctx->num_cus > 0 ? ctx->num_cus : 256);
+        if (plan.ksplit > 1) {   // partial sums only: the TCEC form adds them in a second kernel
+            if (sb) {
+                if (plan.partial_bytes > sb->partial_bytes)
+                    return fail(ctx, RP_ERR_INVALID_ARG, "workspace too small for the contraction split");
+                a.partial = sb->partial;
+            } else {
+                rp_status st = ensure_split_workspace(ctx, 0, plan.partial_bytes);
+                if (st != RP_OK) return st;
+                a.partial = static_cast<float*>(ctx->split_ws);
+            }
+            a.ksplit = plan.ksplit;
+        }
+        RP_HIP(ctx, rpmi::launch_project_tcec(a, s));
+        return RP_OK;
+    }
     if (algo == RP_ALGO_SPLIT_F16) {
         a.fold_flags = ctx->fold_flags;
         a.fold_epoch = ++ctx->fold_epoch;
@@ -635,7 +678,7 @@ rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const*
 extern "C" {
 
 rp_status rp_omega_packed_size(int64_t n, int64_t r, rp_algo_t algo, size_t* bytes) {
-    if (!bytes || n < 0 || r < 0 || (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16))
+    if (!bytes || n < 0 || r < 0 || (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16 && algo != RP_ALGO_TCEC_F16))
         return fail(nullptr, RP_ERR_INVALID_ARG, "invalid arguments to rp_omega_packed_size");
     *bytes = packed_bytes(packed_geometry(n, r, algo, nullptr), algo);
     return RP_OK;
@@ -667,7 +710,7 @@ rp_status rp_project_packed(rp_ctx ctx, const rp_desc* A, int64_t r, const void*
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!desc_ok(ctx, A, &st)) return st;
-    if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16)
+    if (algo != RP_ALGO_F32 && algo != RP_ALGO_SPLIT_F16 && algo != RP_ALGO_TCEC_F16)
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown algorithm %d", (int)algo);
     if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
     if (r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative r %lld", (long long)r);
@@ -819,16 +862,21 @@ rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy,
 // fragment order for the power scheme's projections.
 struct RsvdScratch {
     int64_t m = 0, n = 0, k = 0, p = 0;
-    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_gp, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_jt, o_jf, bytes;
+    size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_gp, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_pkq, o_jt, o_jf,
+        bytes;
     float *Q, *Z, *W;
     double *Qd, *G, *X, *L1, *GP, *MW, *MV, *sig, *Ur, *Vr;
     int* ord;
     int* jflags;                       // Jacobi flags (4 ints)
+    bool tcec_aw = false;              // power scheme's A W on the TCEC products (pkw in TCEC form)
+    bool tcec_atq = false;             // A^T Q on the TCEC products (Q packed into pkq)
+    const SplitBuffers* aw_sb = nullptr;   // contraction-split buffers for A W (else the context's)
     rpmi::JacobiProb* jtab;            // a one-entry Jacobi table (device)
     rpmi::PackedOmega pkw;
+    rpmi::PackedOmega pkq;             // Q (m x p) in TCEC fragment form, for A^T Q
 
     // reserve the scratch in `ar` (one block); returns its offset
-    size_t layout(Arena& outer, int64_t m_, int64_t n_, int64_t k_, int64_t p_) {
+    size_t layout(Arena& outer, int64_t m_, int64_t n_, int64_t k_, int64_t p_, bool tcec_room = true) {
         m = m_; n = n_; k = k_; p = p_;
         Arena ar;
         const int64_t mx = m > n ? m : n;
@@ -848,6 +896,8 @@ struct RsvdScratch {
         o_vr = ar.take((size_t)p * k * 8);
         pkw = packed_geometry(n, p, RP_ALGO_F32, nullptr);
         o_pkw = ar.take(packed_bytes(pkw, RP_ALGO_F32));
+        pkq = packed_geometry(m, p, RP_ALGO_TCEC_F16, nullptr);
+        o_pkq = ar.take(tcec_room ? packed_bytes(pkq, RP_ALGO_TCEC_F16) : 0);
         o_jt = ar.take(sizeof(rpmi::JacobiProb));
         o_jf = ar.take(4 * sizeof(int));
         bytes = ar.used;
@@ -869,6 +919,7 @@ struct RsvdScratch {
         Ur = reinterpret_cast<double*>(b + o_ur);
         Vr = reinterpret_cast<double*>(b + o_vr);
         pkw.data = b + o_pkw;
+        pkq.data = b + o_pkq;
         jtab = reinterpret_cast<rpmi::JacobiProb*>(b + o_jt);
         jflags = reinterpret_cast<int*>(b + o_jf);
     }
@@ -896,9 +947,28 @@ rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) 
 // (re-orthonormalised), then Q = QR(Y), B^T = A^T Q, B^T = Q_B R_B with R_B^T
 // left in w.MW.  Launches kernels only (capturable in a graph).
 // Z = A^T Q (n x p, row-major) for A (m x n, lda) and Q (m x p).
+// With `pkq` (TCEC form, m x p) the product takes the TCEC kernel (eq:tcec-5,
+// Q packed first), else the FP32 matrix-core kernel.  `report_q` records an
+// entry |q| >= 32 as RP_ERR_OMEGA_RANGE (a caller's Q; the algorithms' own
+// orthonormal Q is inside the range unless A already was not finite, which
+// its own report covers).
 rp_status gemm_at_q(rp_ctx ctx, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda, const float* Q,
-                    float* Z, hipStream_t s) {
-    RP_HIP(ctx, rpmi::gemm_tn_f32(n, p, m, A, lda, Q, p, Z, p, s));
+                    int64_t ldq, float* Z, int64_t ldz, const rpmi::PackedOmega* pkq, hipStream_t s,
+                    bool report_q = false) {
+    if (!pkq) {
+        RP_HIP(ctx, rpmi::gemm_tn_f32(n, p, m, A, lda, Q, ldq, Z, ldz, s));
+        return RP_OK;
+    }
+    RP_HIP(ctx, rpmi::launch_pack_omega_tcec(Q, m, p, ldq, *pkq, report_q ? ctx->d_status : nullptr,
+                                             rpmi::kStatusOmegaRange, s));
+    rpmi::TnTcecArgs t;
+    t.A = A; t.lda = lda; t.m = m; t.n = n; t.p = p;
+    t.qhi = pkq->data;
+    t.qlo = static_cast<const char*>(pkq->data) + (size_t)pkq->kb_count * pkq->nt_count * 64 * 8 * 2;
+    t.nt_count = pkq->nt_count;
+    t.Z = Z; t.ldz = ldz;
+    t.status = ctx->d_status;
+    RP_HIP(ctx, rpmi::launch_gemm_tn_tcec(t, s));
     return RP_OK;
 }
 
@@ -910,17 +980,26 @@ rp_status rsvd_before_svd(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_problem& 
     for (int32_t t = 0; t < power_iters; ++t) {
         if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
         // Z = A^T Q (n x p)
-        if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
+        if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, p, w.Z, p, w.tcec_atq ? &w.pkq : nullptr, s)) != RP_OK)
+            return st;
         if ((st = cholqr2(ctx, n, p, w.Z, p, w.W, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
-        // Y = A W (FP32 x FP32): the FP32 projection kernel with W in fragment order
-        RP_HIP(ctx, rpmi::launch_pack_omega(w.W, rpmi::OmegaSrc::F32, nullptr, n, p, p, w.pkw, true, nullptr, 0, nullptr,
-                                            s));
-        if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
+        // Y = A W (FP32 x FP32, W not random): the TCEC products (eq:tcec-5) or
+        // the FP32 projection kernel, with W in fragment order (|w| <= 1: W
+        // has orthonormal columns)
+        if (w.tcec_aw) {
+            RP_HIP(ctx, rpmi::launch_pack_omega_tcec(w.W, n, p, p, w.pkw, nullptr, 0, s));
+            if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_TCEC_F16, Y, p, s, 0, false, w.aw_sb)) != RP_OK)
+                return st;
+        } else {
+            RP_HIP(ctx, rpmi::launch_pack_omega(w.W, rpmi::OmegaSrc::F32, nullptr, n, p, p, w.pkw, true, nullptr, 0,
+                                                nullptr, s));
+            if ((st = launch_projection(ctx, &dA, p, w.pkw, RP_ALGO_F32, Y, p, s)) != RP_OK) return st;
+        }
     }
     // Algorithm 1 line 2: Q = QR(Y)
     if ((st = cholqr2(ctx, m, p, Y, p, w.Q, p, nullptr, w.Qd, w.G, w.X, w.L1, w.GP, s)) != RP_OK) return st;
     // line 3: B^T = A^T Q (n x p)
-    if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, w.Z, s)) != RP_OK) return st;
+    if ((st = gemm_at_q(ctx, m, n, p, A, lda, w.Q, p, w.Z, p, w.tcec_atq ? &w.pkq : nullptr, s)) != RP_OK) return st;
     // line 4: B^T = Q_B R_B; R_B^T = L1 L2 (p x p lower) into MW
     return cholqr2(ctx, n, p, w.Z, p, w.W, p, w.MW, w.Qd, w.G, w.X, w.L1, w.GP, s);
 }
@@ -974,6 +1053,10 @@ RsvdPlan rsvd_plan(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64_t oversamp
     pl.o_w = pl.w.layout(ar, m, n, k, p);
     pl.sp = algo == RP_ALGO_SPLIT_F16 ? rpmi::plan_split_f16(m, n, p, ctx->num_cus > 0 ? ctx->num_cus : 256)
                                       : rpmi::SplitPlan{1, 0, 0};
+    if (algo == RP_ALGO_SPLIT_F16) {   // the same buffer serves the power scheme's TCEC A W
+        const rpmi::SplitPlan tp = rpmi::plan_tcec(m, n, p, ctx->num_cus > 0 ? ctx->num_cus : 256);
+        if (tp.partial_bytes > pl.sp.partial_bytes) pl.sp.partial_bytes = tp.partial_bytes;
+    }
     pl.o_cnt = ar.take(pl.sp.counter_bytes);
     pl.o_part = ar.take(pl.sp.partial_bytes);
     pl.bytes = ar.used;
@@ -1192,6 +1275,8 @@ rp_status rsvd_workspace_size(rp_ctx ctx, int64_t m, int64_t n, int64_t k, int64
     if (!bytes) return fail(ctx, RP_ERR_INVALID_ARG, "bytes is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (algo == RP_ALGO_TCEC_F16)
+        return fail(ctx, RP_ERR_INVALID_ARG, "the randomized algorithms project with RP_ALGO_F32 or RP_ALGO_SPLIT_F16");
     const int64_t p = k + oversample;
     if (m <= 0 || n <= 0 || k <= 0 || oversample < 0 || power_iters < 0 || p > m || p > n || p > 1024)
         return fail(ctx, RP_ERR_INVALID_ARG, "invalid sizes (m %lld, n %lld, k %lld, s %lld, q %d)", (long long)m,
@@ -1207,6 +1292,8 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (algo == RP_ALGO_TCEC_F16)
+        return fail(ctx, RP_ERR_INVALID_ARG, "the randomized algorithms project with RP_ALGO_F32 or RP_ALGO_SPLIT_F16");
     if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
     const rp_rsvd_problem prob{m, n, A, lda, k, oversample, U, ldu, S, VT, ldvt};
     if ((st = rsvd_check(ctx, prob, power_iters)) != RP_OK) return st;
@@ -1226,9 +1313,23 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     pk.data = base + pl.o_pk;
     RsvdScratch w = pl.w;
     w.bind(base + pl.o_w);
+    {
+        // the power scheme's A W on the TCEC products when the projection is
+        // split-FP16 and A is on their 16-byte path (pkw has the same size in
+        // both forms; their contraction split uses the projection's buffer)
+        // (with a caller pre-scale, which the TCEC kernels do not take, the
+        // FP32 kernels, which need none)
+        const rpmi::ProjArgs aw = proj_args(ctx, &dA, p, nullptr, 0, nullptr, p, 0);
+        const bool tcec = algo == RP_ALGO_SPLIT_F16 && a_scale_exp == 0 && rpmi::split_fast_ok(aw);
+        w.tcec_aw = tcec && power_iters > 0 &&
+                    packed_geometry(n, p, RP_ALGO_TCEC_F16, nullptr).nt_count == w.pkw.nt_count;
+        // A^T Q (Algorithm 1 line 3 and the power scheme) likewise
+        w.tcec_atq = tcec;
+    }
     float* Y = reinterpret_cast<float*>(base + pl.o_y);
     SplitBuffers sb{reinterpret_cast<unsigned int*>(base + pl.o_cnt), reinterpret_cast<float*>(base + pl.o_part),
                     pl.sp.counter_bytes, pl.sp.partial_bytes};
+    w.aw_sb = &sb;
     if (pl.sp.counter_bytes)
         RP_HIP(ctx, rpmi::launch_fill_u32(sb.counters, (int64_t)(pl.sp.counter_bytes / 4), 0u, s));
     // Algorithm 1 line 1: Y = A Omega (Omega from the context cache, or
@@ -1245,6 +1346,31 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
                                 &sb)) != RP_OK)
         return st;
     return rsvd_after_projection(ctx, dA, prob, p, power_iters, Y, w, s);
+}
+
+rp_status rp_gemm_tn(rp_ctx ctx, int64_t m, int64_t n, int64_t p, const float* A, int64_t lda, const float* Q,
+                     int64_t ldq, rp_algo_t algo, float* Z, int64_t ldz, void* stream) {
+    if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
+    if (m < 0 || n < 0 || p < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative size");
+    if (algo != RP_ALGO_F32 && algo != RP_ALGO_TCEC_F16)
+        return fail(ctx, RP_ERR_INVALID_ARG, "rp_gemm_tn takes RP_ALGO_F32 or RP_ALGO_TCEC_F16");
+    if (n == 0 || p == 0) return RP_OK;
+    if (!A || !Q || !Z) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    if (lda < n || ldq < p || ldz < p) return fail(ctx, RP_ERR_INVALID_ARG, "leading dimension too small");
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    if (m == 0) {
+        RP_HIP(ctx, rpmi::launch_fill_f32(Z, n, p, ldz, 0.0f, s));
+        return RP_OK;
+    }
+    if (algo == RP_ALGO_F32) return gemm_at_q(ctx, m, n, p, A, lda, Q, ldq, Z, ldz, nullptr, s);
+    if ((n & 3) || (lda & 3) || (reinterpret_cast<uintptr_t>(A) & 15))
+        return fail(ctx, RP_ERR_UNSUPPORTED, "the TCEC A^T Q needs n and lda multiples of 4 and a 16-byte aligned A");
+    rpmi::PackedOmega pkq = packed_geometry(m, p, RP_ALGO_TCEC_F16, nullptr);
+    rp_status st;
+    if ((st = ensure_workspace(ctx, packed_bytes(pkq, RP_ALGO_TCEC_F16))) != RP_OK) return st;
+    pkq.data = ctx->ws;
+    return gemm_at_q(ctx, m, n, p, A, lda, Q, ldq, Z, ldz, &pkq, s, true);
 }
 
 rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem* probs, rp_omega_t omega_type,
@@ -1341,7 +1467,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     std::vector<RsvdScratch> ws(count);
     std::vector<size_t> o_ws(count);
     for (int32_t g = 0; g < count; ++g)
-        o_ws[g] = ws[g].layout(ar, probs[g].m, probs[g].n, probs[g].k, probs[g].k + probs[g].oversample);
+        o_ws[g] = ws[g].layout(ar, probs[g].m, probs[g].n, probs[g].k, probs[g].k + probs[g].oversample, false);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     char* base = static_cast<char*>(ctx->ws);
     for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
@@ -1582,6 +1708,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
+    if (algo == RP_ALGO_TCEC_F16)
+        return fail(ctx, RP_ERR_INVALID_ARG, "the randomized algorithms project with RP_ALGO_F32 or RP_ALGO_SPLIT_F16");
     if (ndim < 2 || ndim > rpmi::kMaxGroup)
         return fail(ctx, RP_ERR_INVALID_ARG, "ndim %d outside [2, %d]", (int)ndim, rpmi::kMaxGroup);
     if (!dims || !ranks || !X || !core || !factors) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
@@ -1654,6 +1782,12 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     const size_t o_gp = ar.take((size_t)rpmi::kGramSplit * maxr * maxr * 8);
     const size_t o_t0 = ar.take((size_t)tmax * 4);
     const size_t o_t1 = ar.take((size_t)tmax * 4);
+    // the first core contraction on the TCEC products (split algorithm, X on
+    // their 16-byte path): Q_0 in TCEC fragment form
+    const bool core_tcec = algo == RP_ALGO_SPLIT_F16 && N >= 2 && after[0] % 4 == 0 &&
+                           (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+    rpmi::PackedOmega pkq0 = packed_geometry(dims[0], ranks[0], RP_ALGO_TCEC_F16, nullptr);
+    const size_t o_pkq0 = ar.take(core_tcec ? packed_bytes(pkq0, RP_ALGO_TCEC_F16) : 0);
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     char* base = static_cast<char*>(ctx->ws);
     float* W[rpmi::kMaxGroup];
@@ -1718,7 +1852,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
             return st;
     // core g = X x_1 Q_1^T ... x_N Q_N^T, one mode at a time: T has shape
     // [lead, I_i, after_i]; out[b][j][p] = sum_k Q_i[k][j] T[b][k][p] (the
-    // first mode on FP32 MFMA, the others with FP64 accumulation)
+    // first mode on the TCEC products or FP32 MFMA, the others with FP64
+    // accumulation)
     const float* T = X;
     float* bufs[2] = {reinterpret_cast<float*>(base + o_t0), reinterpret_cast<float*>(base + o_t1)};
     int64_t lead = 1;
@@ -1728,6 +1863,14 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
         if (P == 1) {
             RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(lead, J, I, 1.0, T, I, 1, factors[i], J, 1, 0.0, out, J,
                                                                 1, s)));
+        } else if (lead == 1 && core_tcec) {
+            // out (J x P) = (T^T Q_i)^T: Z = T^T Q_i (P x J, into the other
+            // buffer, free until the next mode) on the TCEC products, then
+            // transposed
+            float* z = bufs[(i + 1) & 1];
+            pkq0.data = base + o_pkq0;
+            if ((st = gemm_at_q(ctx, I, P, J, T, P, factors[i], J, z, J, &pkq0, s)) != RP_OK) return st;
+            RP_HIP(ctx, rpmi::launch_swap01(z, P, J, 1, out, s));
         } else if (lead == 1) {
             // out (J x P) = Q_i^T T: the A^T Q form on FP32 MFMA
             RP_HIP(ctx, rpmi::gemm_tn_f32(J, P, I, factors[i], J, T, P, out, P, s));
@@ -1761,8 +1904,10 @@ rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* o
     unsigned int word = 0;
     RP_HIP(ctx, hipMemcpy(&word, ctx->d_status, sizeof word, hipMemcpyDeviceToHost));
     if (clear) RP_HIP(ctx, hipMemset(ctx->d_status, 0, sizeof(unsigned int)));
-    *out = (word & rpmi::kStatusRange) ? RP_ERR_RANGE
-         : (word & rpmi::kStatusOmegaRange) ? RP_ERR_OMEGA_RANGE
+    // an Omega outside its range also makes the products non-finite: it is
+    // reported first, as the cause
+    *out = (word & rpmi::kStatusOmegaRange) ? RP_ERR_OMEGA_RANGE
+         : (word & rpmi::kStatusRange) ? RP_ERR_RANGE
          : (word & rpmi::kStatusNotSpd) ? RP_ERR_NOT_SPD
          : (word & rpmi::kStatusNotConverged) ? RP_ERR_NOT_CONVERGED
          : RP_OK;

@@ -65,6 +65,10 @@ struct ProjArgs {
     // which changes nothing); fold_epoch is distinct per launch and never 0
     unsigned int* fold_flags = nullptr;
     unsigned int fold_epoch = 0;
+    // TCEC products (both operands split, eq:tcec-5): `omega` holds the FP16
+    // hi fragments of the FP32 right operand and `omega_lo` its FP16
+    // RN16(2^11 (w - hi)) fragments, in the same order
+    const void* omega_lo = nullptr;
 };
 constexpr int kFoldFlags = 4096;      // flag table of the folded split (power of two)
 
@@ -142,6 +146,35 @@ hipError_t launch_pack_omega(const void* src, OmegaSrc type, const float* col_sc
                              int64_t ldo, const PackedOmega& dst, bool dst_f32, unsigned int* flag,
                              unsigned int flag_bit, unsigned int* status, hipStream_t s);
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s);
+// Y = A W for an FP32 W with both operands split (eq:tcec-5): hi_A (2^11 hi_W)
+// + lo_A hi_W + hi_A lo_W on FP16 MFMA into one FP32 accumulator.  Needs the
+// 16-byte path (split_fast_ok) and W packed by launch_pack_omega_tcec.
+hipError_t launch_project_tcec(const ProjArgs& a, hipStream_t s);
+SplitPlan plan_tcec(int64_t m, int64_t n, int64_t r, int num_cus);
+int64_t tcec_col_block();                 // 128
+// Z = A^T Q (Z: n x p, row-major, ldz) for A m x n (row-major, lda) and Q
+// m x p packed by launch_pack_omega_tcec (qhi = data, qlo = the lo
+// fragments), with the TCEC products (eq:tcec-5).  Needs n and lda multiples
+// of 4 and a 16-byte aligned A.  A non-finite product (|a| >= 65520 or a
+// non-finite element) sets kStatusRange in *status.
+struct TnTcecArgs {
+    const float* A = nullptr;
+    int64_t lda = 0;
+    int64_t m = 0, n = 0, p = 0;
+    const void* qhi = nullptr;
+    const void* qlo = nullptr;
+    int64_t nt_count = 0;
+    float* Z = nullptr;
+    int64_t ldz = 0;
+    unsigned int* status = nullptr;
+};
+hipError_t launch_gemm_tn_tcec(const TnTcecArgs& t, hipStream_t s);
+// Pack a row-major FP32 W (n x r, leading dimension ldo) for the TCEC
+// kernels: FP16 hi fragments at dst.data, then the RN16(2^11 (w - hi))
+// fragments; |hi| >= 32 or a non-finite value sets `flag_bit` in *flag (the
+// hi products take 2^11 hi_W, exact in FP16 below 32).
+hipError_t launch_pack_omega_tcec(const float* src, int64_t n, int64_t r, int64_t ldo, const PackedOmega& dst,
+                                  unsigned int* flag, unsigned int flag_bit, hipStream_t s);
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s);
 hipError_t launch_split_dump(const float* x, int64_t count, uint16_t* hi, uint16_t* lo,
                              hipStream_t s);

