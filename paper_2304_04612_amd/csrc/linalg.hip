@@ -318,10 +318,25 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     if (c >= n) return;                               // the dummy of an odd n
     double* wa = P.W + (int64_t)a * n;
     double* wc = P.W + (int64_t)c * n;
+    double* va = P.V + (int64_t)a * n;
+    double* vc = P.V + (int64_t)c * n;
+    // all four columns' elements of this thread in registers at once (n <=
+    // 1024): one memory round trip before the reduction, none after it
+    constexpr int PER = 1024 / STRIDE;
+    double x[PER], y[PER], vx[PER], vy[PER];
     double al = 0.0, be = 0.0, ga = 0.0;
-    for (int r = t0; r < n; r += STRIDE) {
-        const double x = wa[r], y = wc[r];
-        al += x * x; be += y * y; ga += x * y;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int r = t0 + u * STRIDE;
+        const bool in = r < n;
+        x[u] = in ? wa[r] : 0.0;
+        y[u] = in ? wc[r] : 0.0;
+        vx[u] = in ? va[r] : 0.0;
+        vy[u] = in ? vc[r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        al += x[u] * x[u]; be += y[u] * y[u]; ga += x[u] * y[u];
     }
     if constexpr (WAVE) {
         // butterfly: every lane ends with the same bits, so the lanes agree
@@ -341,17 +356,165 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
     const double zeta = (be - al) / (2.0 * ga);
     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-    double* va = P.V + (int64_t)a * n;
-    double* vc = P.V + (int64_t)c * n;
-    for (int r = t0; r < n; r += STRIDE) {
-        const double x = wa[r], y = wc[r];
-        wa[r] = cs * x - sn * y;
-        wc[r] = sn * x + cs * y;
-        const double vx = va[r], vy = vc[r];
-        va[r] = cs * vx - sn * vy;
-        vc[r] = sn * vx + cs * vy;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int r = t0 + u * STRIDE;
+        if (r < n) {
+            wa[r] = cs * x[u] - sn * y[u];
+            wc[r] = sn * x[u] + cs * y[u];
+            va[r] = cs * vx[u] - sn * vy[u];
+            vc[r] = sn * vx[u] + cs * vy[u];
+        }
     }
     if (t0 == 0) P.flags[1 + (sweep & 1)] = 1;
+}
+
+// One round of the block form of the one-sided Jacobi SVD: the columns are
+// grouped in blocks of kJacobiBlock, the blocks are paired by the same
+// round-robin ordering, and one workgroup takes a pair of blocks (up to 16
+// columns of length n): it forms their 16 x 16 Gram H on FP64 MFMA, runs one
+// cyclic sweep of the rotations of Algorithm 1's SVD on H (each rotation the
+// one that zeroes H[p][q], as the column form computes it from the same dot
+// products), accumulating them in Qm, and applies Qm to the block's columns
+// of W and V.  Every pair of columns meets within some block pair in every
+// sweep, so a sweep does at least the rotations of a column sweep, with
+// p / 8 - 1 launches instead of p - 1.  A block paired with the padding block
+// (odd block count) or a partial last block just has fewer columns.
+__global__ __launch_bounds__(256) void jacobi_block_round_kernel(const JacobiProb* tab, int count, int total_bpairs,
+                                                                 int round, int sweep, double tol) {
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    constexpr int JB = kJacobiBlock, JV = 2 * kJacobiBlock;   // 16 columns per block pair
+    const int b = blockIdx.x;
+    if (b >= total_bpairs) return;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].bpair_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const JacobiProb P = tab[lo];
+    const int n = P.n, nb = (n + JB - 1) / JB, m = nb + (nb & 1);
+    if (round >= m - 1 || P.flags[0]) return;
+    const int k = b - P.bpair_start;
+    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
+    const int bi = player(k), bj = player(m - 1 - k);
+
+    __shared__ int vid[JV];
+    __shared__ double Hp[4][JV][JV + 1];
+    __shared__ double H[JV][JV + 1];
+    __shared__ double Qm[JV][JV + 1];
+    __shared__ double rc[JV / 2], rs[JV / 2];
+    __shared__ int rot_any;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < JV) {
+        const int blk = tid < JB ? bi : bj, col = blk * JB + (tid % JB);
+        vid[tid] = blk < nb && col < n ? col : -1;   // -1: no column (padding block, ragged end)
+    }
+    if (tid == 0) rot_any = 0;
+    __syncthreads();
+
+    // H = Wp Wp^T over the n rows: wave w takes rows [w R, (w + 1) R); lane l
+    // holds W[vid[l mod 16]][r] for r = l / 16 + 4 s, which is both MFMA
+    // operands (A[i][k] and B[k][j] of the same column set)
+    {
+        const int v = lane & 15, kk = lane >> 4;
+        const int R = ((n + 15) / 16) * 4;            // rows per wave, a multiple of 4
+        const int r0 = wave * R;
+        const double* wv = vid[v] >= 0 ? P.W + (int64_t)vid[v] * n : nullptr;
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+        constexpr int CH = 16;   // loads issued together, then their matrix instructions
+        for (int r1 = r0 + kk; r1 < r0 + R; r1 += 4 * CH) {
+            double xs[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int r = r1 + 4 * u;
+                xs[u] = (wv && r < r0 + R && r < n) ? wv[r] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[u], xs[u], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Hp[wave][kk + 4 * e][v] = acc[e];
+    }
+    __syncthreads();
+    {
+        const int i = tid / JV, j = tid % JV;
+        H[i][j] = (Hp[0][i][j] + Hp[1][i][j]) + (Hp[2][i][j] + Hp[3][i][j]);
+        Qm[i][j] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+
+    // one cyclic sweep over the 16 local columns (round-robin, 8 disjoint
+    // pairs per inner round); a rotation R = [[c, -s], [s, c]] on columns
+    // (p, q) takes rows p, q of Qm and H to R (.) and then columns of H
+    for (int ir = 0; ir < JV - 1; ++ir) {
+        auto lp = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + ir) % (JV - 1); };
+        if (tid < JV / 2) {
+            int p = lp(tid), q = lp(JV - 1 - tid);
+            if (p > q) { const int t = p; p = q; q = t; }
+            const double al = H[p][p], be = H[q][q], ga = H[p][q];
+            double c = 1.0, sn = 0.0;
+            if (fabs(ga) > tol * sqrt(al * be) && ga != 0.0) {
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                c = 1.0 / sqrt(1.0 + t * t);
+                sn = c * t;
+                rot_any = 1;
+            }
+            rc[tid] = c;
+            rs[tid] = sn;
+        }
+        __syncthreads();
+        {   // rows: 8 pairs x 16 columns of H, and of Qm
+            const int t = tid >> 5, col = tid & 15, which = (tid >> 4) & 1;   // which: H or Qm
+            int p = lp(t), q = lp(JV - 1 - t);
+            if (p > q) { const int u = p; p = q; q = u; }
+            const double c = rc[t], sn = rs[t];
+            double (*M)[JV + 1] = which ? Qm : H;
+            const double xp = M[p][col], xq = M[q][col];
+            M[p][col] = c * xp - sn * xq;
+            M[q][col] = sn * xp + c * xq;
+        }
+        __syncthreads();
+        if (tid < 128) {   // columns of H
+            const int t = tid >> 4, row = tid & 15;
+            int p = lp(t), q = lp(JV - 1 - t);
+            if (p > q) { const int u = p; p = q; q = u; }
+            const double c = rc[t], sn = rs[t];
+            const double xp = H[row][p], xq = H[row][q];
+            H[row][p] = c * xp - sn * xq;
+            H[row][q] = sn * xp + c * xq;
+        }
+        __syncthreads();
+    }
+    if (!rot_any) return;
+    if (tid == 0) P.flags[1 + (sweep & 1)] = 1;
+
+    // W_new[i][r] = sum_j Qm[i][j] W[j][r] (and V), each thread its own rows r
+    // (n <= 1024: up to 4 per thread, all loaded before any is used)
+    for (int which = 0; which < 2; ++which) {
+        double* base = which ? P.V : P.W;
+        double x[4][JV];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = tid + 256 * u;
+#pragma unroll
+            for (int j = 0; j < JV; ++j) x[u][j] = (r < n && vid[j] >= 0) ? base[(int64_t)vid[j] * n + r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = tid + 256 * u;
+            if (r >= n) continue;
+#pragma unroll
+            for (int i = 0; i < JV; ++i) {
+                if (vid[i] < 0) continue;
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < JV; ++j) acc += Qm[i][j] * x[u][j];
+                base[(int64_t)vid[i] * n + r] = acc;
+            }
+        }
+    }
 }
 
 __global__ void set_jacobi_prob_kernel(JacobiProb* dst, JacobiProb v) {
@@ -598,17 +761,31 @@ hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t 
     return hipSuccess;
 }
 
-hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
-                            double tol, unsigned int* status, hipStream_t s, const int* poll_flag) {
+hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n,
+                            int max_sweeps, double tol, unsigned int* status, hipStream_t s, const int* poll_flag) {
     if (count <= 0 || max_n <= 0) return hipSuccess;
+    if (max_n > 1024) return hipErrorInvalidValue;    // the round kernels hold n <= 1024 elements in registers
     hipError_t e;
     const int gx = grid1d((int64_t)max_n * max_n) < 1024 ? grid1d((int64_t)max_n * max_n) : 1024;
     hipLaunchKernelGGL(jacobi_prep_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int max_m = max_n + (max_n & 1);
+    // the block form once a problem has more than one block pair per round.
+    // Its rotations come from the block's Gram, whose rounding keeps the
+    // last off-diagonal ratios near 1e-13 for a while (16 sweeps instead of
+    // 14 on a 640 x 640 R_B^T with sigma in [0.018, 1] at 1e-12), so it stops
+    // at 1e-12 (singular values then agree to far below FP32 rounding) and
+    // may take up to 8 more sweeps.
+    const bool block = max_n > 2 * kJacobiBlock;
+    const int max_nb = (max_n + kJacobiBlock - 1) / kJacobiBlock;
+    const int max_m = block ? max_nb + (max_nb & 1) : max_n + (max_n & 1);
+    const double btol = tol > 1e-12 ? tol : 1e-12;
+    if (block) max_sweeps += 8;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int round = 0; round < max_m - 1; ++round) {
-            if (total_pairs >= kJacobiWavePairs)
+            if (block)
+                hipLaunchKernelGGL(jacobi_block_round_kernel, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab, count,
+                                   total_bpairs, round, sweep, btol);
+            else if (total_pairs >= kJacobiWavePairs)
                 hipLaunchKernelGGL(jacobi_round_kernel<true>, dim3((unsigned)((total_pairs + 3) / 4)), dim3(256), 0, s,
                                    tab, count, total_pairs, round, sweep, tol);
             else

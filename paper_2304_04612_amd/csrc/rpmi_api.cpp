@@ -1020,13 +1020,14 @@ rp_status rsvd_after_projection(rp_ctx ctx, const rp_desc& dA, const rp_rsvd_pro
                                 int32_t power_iters, float* Y, const RsvdScratch& w, hipStream_t s) {
     rp_status st;
     if ((st = rsvd_before_svd(ctx, dA, q, p, power_iters, Y, w, s)) != RP_OK) return st;
-    RP_HIP(ctx, rpmi::launch_set_jacobi_prob(w.jtab, rpmi::JacobiProb{w.MW, w.MV, (int)p, 0, w.jflags}, s));
+    RP_HIP(ctx, rpmi::launch_set_jacobi_prob(w.jtab, rpmi::JacobiProb{w.MW, w.MV, (int)p, 0, w.jflags, 0}, s));
     // outside graph capture the sweeps stop at convergence (the host polls the
     // converged flag once per sweep); under capture all sweeps are recorded and
     // a converged problem's kernels return at once
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     RP_HIP(ctx, hipStreamIsCapturing(s, &cap));
-    RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), (int)p, kJacobiSweeps, kJacobiTol,
+    RP_HIP(ctx, rpmi::jacobi_svd_group(w.jtab, 1, (int)((p + 1) / 2), rpmi::jacobi_block_pairs((int)p), (int)p,
+                                       kJacobiSweeps, kJacobiTol,
                                        ctx->d_status, s, cap == hipStreamCaptureStatusNone ? w.jflags : nullptr));
     return rsvd_after_svd(ctx, q, p, w, s);
 }
@@ -1564,11 +1565,12 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                               hipMemcpyHostToDevice));
     }
     std::vector<rpmi::JacobiProb> jt(count);
-    int jpairs = 0;
+    int jpairs = 0, jbpairs = 0;
     for (int32_t g = 0; g < count; ++g) {
         const int p = (int)(probs[g].k + probs[g].oversample);
-        jt[g] = rpmi::JacobiProb{ws[g].MW, ws[g].MV, p, jpairs, ws[g].jflags};
+        jt[g] = rpmi::JacobiProb{ws[g].MW, ws[g].MV, p, jpairs, ws[g].jflags, jbpairs};
         jpairs += (p + 1) / 2;
+        jbpairs += rpmi::jacobi_block_pairs(p);
     }
     if ((size_t)count > ctx->graph_jtab_entries) {
         if (ctx->graph_jtab) RP_HIP(ctx, hipFree(ctx->graph_jtab));
@@ -1678,7 +1680,8 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
             }
         }
         // one parallel Jacobi SVD over every problem's R_B^T
-        RP_HIP(ctx, rpmi::jacobi_svd_group(jtab, count, jpairs, (int)mp, kJacobiSweeps, kJacobiTol, ctx->d_status, cs));
+        RP_HIP(ctx, rpmi::jacobi_svd_group(jtab, count, jpairs, jbpairs, (int)mp, kJacobiSweeps, kJacobiTol,
+                                           ctx->d_status, cs));
         if (grouped_stages) return run_finish_group(ctx, fin, aux, cs);
         for (int32_t g = 0; g < count; ++g)
             if ((r2 = rsvd_after_svd(ctx, probs[g], probs[g].k + probs[g].oversample, ws[g], cs)) != RP_OK) return r2;

@@ -215,15 +215,22 @@ struct JacobiProb {
     double* W;
     double* V;
     int n;
-    int pair_start;
+    int pair_start;     // first global column pair of this problem (scalar rounds)
     int* flags;
+    int bpair_start;    // first global block pair (block rounds: blocks of kJacobiBlock columns)
 };
+constexpr int kJacobiBlock = 8;
+// block pairs of one problem per round: ceil(n / 8) blocks, padded to even, halved
+inline int jacobi_block_pairs(int n) {
+    const int nb = (n + kJacobiBlock - 1) / kJacobiBlock;
+    return (nb + (nb & 1)) / 2;
+}
 // Write one Jacobi table entry from the kernel arguments (no host copy).
 hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStream_t s);
 // poll_flag != NULL (a single problem, stream not being captured): the
 // host reads that device flag (the problem's flags[0], "converged") after
 // every sweep, synchronising the stream, and stops issuing sweeps once set.
-hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int max_n, int max_sweeps,
+hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n, int max_sweeps,
                             double tol, unsigned int* status, hipStream_t s, const int* poll_flag = nullptr);
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
