@@ -49,35 +49,44 @@ __global__ __launch_bounds__(256) void gemm_acc64_kernel(
 
 // ---------------------------------------------------------------- Cholesky
 // Factor the nb x nb diagonal block at (k, k) in place (lower), in LDS.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int64_t lda, int64_t k, int nb,
-                                                         unsigned int* status) {
-    __shared__ double T[NB][NB + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 256) T[e / nb][e % nb] = A[(k + e / nb) * lda + k + e % nb];
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        __shared__ double d;
-        if (tid == 0) {
-            double v = T[j][j];
-            if (!(v > 0.0)) {             // breakdown (or NaN): record, keep going
-                atomicOr(status, kStatusNotSpd);
-                v = fabs(v) > 0.0 ? fabs(v) : 1.0;
-            }
-            d = sqrt(v);
-            T[j][j] = d;
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The nb x nb diagonal block at (k, k), nb <= 64, factored in place by one
+// wave: lane i holds row i in registers; step j takes the pivot from lane j,
+// scales column j and updates the trailing rows with the column values of
+// lanes l > j read by v_readlane (no LDS, no barriers).
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int64_t lda, int64_t k, int nb,
+                                                        unsigned int* status) {
+    const int i = threadIdx.x;
+    double tr[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) tr[l] = (i < nb && l < nb && l <= i) ? A[(k + i) * lda + k + l] : 0.0;
+    // (rows and columns past nb are zero and stay zero: their pivots are
+    // never taken, and the updates they receive are zero)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double v = readlane_f64(tr[j], j);
+        if (j < nb && !(v > 0.0)) {                  // breakdown (or NaN): record, keep going
+            if (i == 0) atomicOr(status, kStatusNotSpd);
+            v = fabs(v) > 0.0 ? fabs(v) : 1.0;
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < nb; i += 256) T[i][j] /= d;
-        __syncthreads();
-        for (int e = tid; e < (nb - j - 1) * (nb - j - 1); e += 256) {
-            const int i = j + 1 + e / (nb - j - 1), l = j + 1 + e % (nb - j - 1);
-            if (l <= i) T[i][l] -= T[i][j] * T[l][j];
+        const double d = j < nb ? sqrt(v) : 1.0;
+        tr[j] = i == j ? d : (i > j ? tr[j] / d : tr[j]);
+#pragma unroll
+        for (int l = j + 1; l < NB; ++l) {
+            const double llj = readlane_f64(tr[j], l);
+            tr[l] = i >= l ? tr[l] - tr[j] * llj : tr[l];
         }
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e / nb, l = e % nb;
-        A[(k + i) * lda + k + l] = l <= i ? T[i][l] : 0.0;
+    if (i < nb) {
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+            if (l < nb) A[(k + i) * lda + k + l] = l <= i ? tr[l] : 0.0;
     }
 }
 
@@ -827,7 +836,7 @@ hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, 
     if ((e = launch_zero_upper(A, lda, p, s)) != hipSuccess) return e;
     for (int64_t k = 0; k < p; k += NB) {
         const int nb = (int)(p - k < NB ? p - k : NB);
-        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, A, lda, k, nb, status);
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, s, A, lda, k, nb, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t below = p - k - nb;
         if (below <= 0) break;
