@@ -28,15 +28,15 @@ namespace rpmi {
 namespace {
 
 // ------------------------------------------------------------------ split-FP16 kernel
+// One (bm, bn) tile of Y = A Omega, the whole contraction.
 template <class T, int D, bool VEC>
-__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjArgs p) {
+__device__ __forceinline__ void split_f16_body(const ProjArgs& p, int64_t bm, int64_t bn) {
     __shared__ half8 lds[2][T::KS * T::NTB * 64];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int wm = wave % T::WM, wn = wave / T::WM;
-    const int64_t bm = blockIdx.x, bn = blockIdx.y;
     // recomputation after a folded launch: only the rows of marked blocks
     if (p.fold_flags && p.fold_flags[((bm * T::BM) / WideCfg::BM) & (kFoldFlags - 1)] != p.fold_epoch) return;
 
@@ -124,6 +124,31 @@ __global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjAr
                     p.Y[row * p.ldy + col] = (acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f) * p.y_scale;
             }
         }
+}
+
+template <class T, int D, bool VEC>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_kernel(ProjArgs p) {
+    split_f16_body<T, D, VEC>(p, blockIdx.x, blockIdx.y);
+}
+
+// Several projections off the 16-byte path in one launch (element loads,
+// whole contraction per tile): dense block b (see xcd_dense_block) belongs to
+// the problem g with table[g].start <= b < table[g + 1].start; inside it,
+// blocks enumerate (bm, bn) with bn fastest.
+template <class T, int D>
+__global__ __launch_bounds__(T::THREADS, 1) void project_split_f16_general_grouped_kernel(
+    const GroupEntry* __restrict__ table, int count) {
+    const int64_t b = xcd_dense_block(blockIdx.x, gridDim.x);
+    int lo = 0, hi = count - 1;
+#pragma unroll 1
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupEntry& e = table[lo];
+    const int64_t local = b - e.start;
+    split_f16_body<T, D, false>(e.p, local / e.tiles_n, local % e.tiles_n);
 }
 
 // ------------------------------------------------------------------ FP32 kernel
@@ -363,6 +388,22 @@ hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
 hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
     return a.r <= kNarrowMax ? launch_split_with<NarrowCfg, SplitTile128>(a, s)
                                   : launch_split_with<WideCfg, SplitTile>(a, s);
+}
+
+int64_t split_general_tile_m(int64_t r) { return r <= kNarrowMax ? SplitTile128::BM : SplitTile::BM; }
+int64_t split_general_tile_n(int64_t r) { return r <= kNarrowMax ? SplitTile128::BN : SplitTile::BN; }
+
+hipError_t launch_project_split_f16_general_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
+                                                    hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (narrow)
+        hipLaunchKernelGGL((project_split_f16_general_grouped_kernel<SplitTile128, kSplitDepth>), dim3((unsigned)blocks),
+                           dim3(SplitTile128::THREADS), 0, s, table, count);
+    else
+        hipLaunchKernelGGL((project_split_f16_general_grouped_kernel<SplitTile, kSplitDepth>), dim3((unsigned)blocks),
+                           dim3(SplitTile::THREADS), 0, s, table, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_project_f32(const ProjArgs& a, hipStream_t s) {

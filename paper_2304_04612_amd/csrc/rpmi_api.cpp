@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -577,85 +578,116 @@ rp_status ensure_table(rp_ctx ctx, size_t entries) {
     return RP_OK;
 }
 
-// Plan a set of split-FP16 projections for one grouped launch per column
-// width: each problem's contraction split is planned for its share of the
-// compute units (in proportion to its A bytes, times `cu_scale`), the split-K
-// counters and partials are laid out in the context buffers, and the table
-// entries (narrow ones first) are returned with the block count of each
-// width.  Problems must be on the 16-byte path (split_fast_ok).
+// Plan a set of split-FP16 projections as at most four grouped launches:
+// problems on the 16-byte path (split_fast_ok) go to the fast kernels, one
+// launch per column width, each with its contraction split planned for its
+// share of the compute units (in proportion to its A bytes, times
+// `cu_scale`) and its split-K counters and partials laid out in the context
+// buffers; the others go to the general kernel, one launch per column width,
+// longest contraction first (each of its tiles runs the whole contraction).
+// Table order: fast narrow, fast wide, general narrow, general wide.
 struct GroupPlan {
+    struct Seg {
+        int first = 0, count = 0;
+        int64_t blocks = 0;
+    };
     std::vector<rpmi::GroupEntry> entries;
-    int narrow_count = 0;
-    int64_t narrow_blocks = 0, wide_blocks = 0;
+    Seg seg[4];   // fast narrow, fast wide, general narrow, general wide
 };
 
 rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, double cu_scale, GroupPlan* out) {
+    std::vector<int> fast, general;
     double total = 0;
-    for (const auto& a : probs) total += (double)a.m * a.n;
-    const int cus = ctx->num_cus > 0 ? ctx->num_cus : 256;
-    std::vector<rpmi::SplitPlan> plans(probs.size());
-    size_t counter_bytes = 0, partial_bytes = 0;
     for (size_t g = 0; g < probs.size(); ++g) {
+        if (rpmi::split_fast_ok(probs[g])) {
+            fast.push_back((int)g);
+            total += (double)probs[g].m * probs[g].n;
+        } else {
+            general.push_back((int)g);
+        }
+    }
+    std::stable_sort(general.begin(), general.end(),
+                     [&](int x, int y) { return probs[x].n > probs[y].n; });
+    const int cus = ctx->num_cus > 0 ? ctx->num_cus : 256;
+    std::vector<rpmi::SplitPlan> plans(probs.size(), rpmi::SplitPlan{1, 0, 0});
+    size_t counter_bytes = 0, partial_bytes = 0;
+    for (int g : fast) {
         const auto& a = probs[g];
         const int share = (int)(cus * cu_scale * ((double)a.m * a.n / total) + 0.5);
         plans[g] = rpmi::plan_split_f16(a.m, a.n, a.r, share > 0 ? share : 1);
         counter_bytes += (plans[g].counter_bytes + 255) & ~size_t(255);
         partial_bytes += (plans[g].partial_bytes + 255) & ~size_t(255);
     }
-    rp_status st = ensure_split_workspace(ctx, counter_bytes, partial_bytes);
-    if (st != RP_OK) return st;
+    if (!fast.empty()) {
+        rp_status st = ensure_split_workspace(ctx, counter_bytes, partial_bytes);
+        if (st != RP_OK) return st;
+    }
     char* cbase = reinterpret_cast<char*>(ctx->split_counters);
     char* pbase = static_cast<char*>(ctx->split_ws);
     out->entries.clear();
-    out->narrow_count = 0;
-    out->narrow_blocks = out->wide_blocks = 0;
-    for (int pass = 0; pass < 2; ++pass) {           // narrow problems, then wide ones
+    for (int sg = 0; sg < 4; ++sg) {
+        const bool gen = sg >= 2, narrow = (sg & 1) == 0;
+        GroupPlan::Seg& seg = out->seg[sg];
+        seg.first = (int)out->entries.size();
         int64_t start = 0;
-        for (size_t g = 0; g < probs.size(); ++g) {
-            const bool narrow = probs[g].r <= 128;
-            if (narrow != (pass == 0)) continue;
+        for (int g : gen ? general : fast) {
+            if ((probs[g].r <= 128) != narrow) continue;
             rpmi::GroupEntry e;
             e.p = probs[g];
-            e.p.ksplit = plans[g].ksplit;
-            e.p.counters = e.p.ksplit > 1 ? reinterpret_cast<unsigned int*>(cbase) : nullptr;
-            e.p.partial = e.p.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
-            cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
-            pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
-            const int64_t bm = rpmi::split_group_tile_m(e.p.r), bn = rpmi::split_group_tile_n(e.p.r);
+            int64_t bm, bn;
+            if (gen) {
+                e.p.ksplit = 1;
+                e.p.counters = nullptr;
+                e.p.partial = nullptr;
+                e.p.fold_flags = nullptr;
+                bm = rpmi::split_general_tile_m(e.p.r);
+                bn = rpmi::split_general_tile_n(e.p.r);
+            } else {
+                e.p.ksplit = plans[g].ksplit;
+                e.p.counters = e.p.ksplit > 1 ? reinterpret_cast<unsigned int*>(cbase) : nullptr;
+                e.p.partial = e.p.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
+                cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
+                pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
+                bm = rpmi::split_group_tile_m(e.p.r);
+                bn = rpmi::split_group_tile_n(e.p.r);
+            }
             e.tiles_m = (e.p.m + bm - 1) / bm;
             e.tiles_n = (e.p.r + bn - 1) / bn;
             e.start = start;
             start += e.tiles_m * e.tiles_n * e.p.ksplit;
             out->entries.push_back(e);
         }
-        if (pass == 0) {
-            out->narrow_count = (int)out->entries.size();
-            out->narrow_blocks = start;
-        } else {
-            out->wide_blocks = start;
-        }
+        seg.count = (int)out->entries.size() - seg.first;
+        seg.blocks = start;
     }
     return RP_OK;
 }
 
-// Write a planned group to `table` (device, stream-ordered) and launch it:
-// one launch per column width present.
+// Launch a planned group whose table is already on the device.
+rp_status launch_group_kernels(rp_ctx ctx, const GroupPlan& gp, const rpmi::GroupEntry* table, hipStream_t s) {
+    for (int sg = 0; sg < 4; ++sg) {
+        const GroupPlan::Seg& seg = gp.seg[sg];
+        if (seg.count == 0) continue;
+        if (sg < 2)
+            RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table + seg.first, seg.count, seg.blocks, sg == 0, s));
+        else
+            RP_HIP(ctx, rpmi::launch_project_split_f16_general_grouped(table + seg.first, seg.count, seg.blocks,
+                                                                       sg == 2, s));
+    }
+    return RP_OK;
+}
+
+// Write a planned group to `table` (device, stream-ordered) and launch it.
 rp_status launch_group(rp_ctx ctx, const GroupPlan& gp, rpmi::GroupEntry* table, hipStream_t s) {
     if (gp.entries.empty()) return RP_OK;
     RP_HIP(ctx, hipMemcpyAsync(table, gp.entries.data(), gp.entries.size() * sizeof(rpmi::GroupEntry),
                                hipMemcpyHostToDevice, s));
-    const int wide_count = (int)gp.entries.size() - gp.narrow_count;
-    if (gp.narrow_count > 0)
-        RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table, gp.narrow_count, gp.narrow_blocks, true, s));
-    if (wide_count > 0)
-        RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table + gp.narrow_count, wide_count, gp.wide_blocks,
-                                                           false, s));
-    return RP_OK;
+    return launch_group_kernels(ctx, gp, table, s);
 }
 
 // Several split-FP16 projections in grouped launches.  Returns
-// RP_ERR_UNSUPPORTED (nothing launched) when a problem is not on the 16-byte
-// path; the caller then launches them one by one.
+// RP_ERR_UNSUPPORTED (nothing launched) when a problem is empty; the caller
+// then launches them one by one.
 rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const* A, const int64_t* r,
                                     const rpmi::PackedOmega* pk, float* const* Y, const int64_t* ldy,
                                     hipStream_t s) {
@@ -664,7 +696,6 @@ rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const*
     for (int g = 0; g < count; ++g) {
         if (A[g]->rows == 0 || A[g]->cols == 0 || r[g] == 0) return RP_ERR_UNSUPPORTED;
         probs[g] = proj_args(ctx, A[g], r[g], pk[g].data, pk[g].nt_count, Y[g], ldy[g], 0);
-        if (!rpmi::split_fast_ok(probs[g])) return RP_ERR_UNSUPPORTED;
     }
     GroupPlan gp;
     rp_status st = plan_group(ctx, probs, 1.0, &gp);
@@ -1417,13 +1448,7 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
         if ((st = fill_packed(ctx, q.seed, q.stream_id, nullptr, 0, nullptr, omega_type, q.A.cols, q.r,
                               RP_ALGO_SPLIT_F16, pk[g], static_cast<char*>(ctx->ws) + o_raw, s)) != RP_OK)
             return st;
-        const rpmi::ProjArgs a = proj_args(ctx, &q.A, q.r, pk[g].data, pk[g].nt_count, q.Y, q.ldy, q.a_scale_exp);
-        if (rpmi::split_fast_ok(a)) {
-            grouped.push_back(a);
-        } else if ((st = launch_projection(ctx, &q.A, q.r, pk[g], RP_ALGO_SPLIT_F16, q.Y, q.ldy, s,
-                                           q.a_scale_exp)) != RP_OK) {
-            return st;
-        }
+        grouped.push_back(proj_args(ctx, &q.A, q.r, pk[g].data, pk[g].nt_count, q.Y, q.ldy, q.a_scale_exp));
     }
     if (grouped.empty()) return RP_OK;
     GroupPlan gp;
@@ -1474,8 +1499,9 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
     for (int32_t g = 0; g < count; ++g) ws[g].bind(base + o_ws[g]);
 
-    // projections of the 16-byte-path problems go out grouped
-    std::vector<rpmi::ProjArgs> grouped;
+    // split-FP16 projections go out grouped (the 16-byte-path problems to the
+    // fast kernels, the others to the general one)
+    std::vector<rpmi::ProjArgs> grouped, grouped_fast;
     std::vector<int> single;
     uint64_t sig = mix(0, (uint64_t)count);
     for (int32_t g = 0; g < count; ++g) {
@@ -1484,9 +1510,13 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         const int64_t p = q.k + q.oversample;
         const rpmi::ProjArgs a = proj_args(ctx, &dA, p, pk[g].data, pk[g].nt_count,
                                            reinterpret_cast<float*>(base + o_y[g]), p, 0);
-        if (algo == RP_ALGO_SPLIT_F16 && rpmi::split_fast_ok(a)) grouped.push_back(a);
-        else single.push_back(g);
-        sig = mix(mix(mix(sig, (uint64_t)q.m), (uint64_t)q.n), (uint64_t)a.r);
+        if (algo == RP_ALGO_SPLIT_F16) {
+            grouped.push_back(a);
+            if (rpmi::split_fast_ok(a)) grouped_fast.push_back(a);
+        } else {
+            single.push_back(g);
+        }
+        sig = mix(mix(mix(mix(sig, (uint64_t)q.m), (uint64_t)q.n), (uint64_t)a.r), (uint64_t)rpmi::split_fast_ok(a));
     }
 
     // the graph of this exact call: problem set, buffers, options, context buffers
@@ -1521,15 +1551,16 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     if (!ctx->cap_stream) RP_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = ctx->cap_stream;
 
-    // autotuner: the contraction split of every grouped problem follows its
-    // share of the compute units times a scale; the scale is chosen once per
-    // problem-shape signature by timing the grouped projection
+    // autotuner: the contraction split of every grouped problem on the
+    // 16-byte path follows its share of the compute units times a scale; the
+    // scale is chosen once per problem-shape signature by timing the fast
+    // grouped launches
     GroupPlan gp;
     if (!grouped.empty()) {
         auto it = ctx->tuned_scale.find(sig);
         double best = 1.0;
-        if (it != ctx->tuned_scale.end()) {
-            best = it->second;
+        if (it != ctx->tuned_scale.end() || grouped_fast.empty()) {
+            if (it != ctx->tuned_scale.end()) best = it->second;
         } else {
             if ((st = gen_omega(cs)) != RP_OK) return st;
             hipEvent_t e0, e1;
@@ -1537,7 +1568,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
             RP_HIP(ctx, hipEventCreate(&e1));
             float best_ms = 1e30f;
             for (double scale : {0.5, 1.0, 2.0, 4.0}) {
-                if ((st = plan_group(ctx, grouped, scale, &gp)) != RP_OK) return st;
+                if ((st = plan_group(ctx, grouped_fast, scale, &gp)) != RP_OK) return st;
                 if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
                 if ((st = launch_group(ctx, gp, ctx->table, cs)) != RP_OK) return st;   // warm-up
                 RP_HIP(ctx, hipEventRecord(e0, cs));
@@ -1626,28 +1657,14 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     auto body = [&]() -> rp_status {
         rp_status r2 = gen_omega(cs);
         if (r2 != RP_OK) return r2;
-        if (!gp.entries.empty()) {
-            const int wide = (int)gp.entries.size() - gp.narrow_count;
-            if (gp.narrow_count > 0)
-                RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ctx->graph_table, gp.narrow_count,
-                                                                   gp.narrow_blocks, true, cs));
-            if (wide > 0)
-                RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(ctx->graph_table + gp.narrow_count, wide,
-                                                                   gp.wide_blocks, false, cs));
-        }
+        if (!gp.entries.empty() && (r2 = launch_group_kernels(ctx, gp, ctx->graph_table, cs)) != RP_OK) return r2;
         for (int g : single) {
             const rp_rsvd_problem& q = probs[g];
             const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
             const int64_t p = q.k + q.oversample;
-            if (algo == RP_ALGO_SPLIT_F16) {
-                // off the 16-byte path: the general split kernel (no table)
-                const rpmi::ProjArgs a = proj_args(ctx, &dA, p, pk[g].data, pk[g].nt_count,
-                                                   reinterpret_cast<float*>(base + o_y[g]), p, 0);
-                RP_HIP(ctx, rpmi::launch_project_split_f16(a, cs));
-            } else if ((r2 = launch_projection(ctx, &dA, p, pk[g], algo, reinterpret_cast<float*>(base + o_y[g]), p,
-                                               cs)) != RP_OK) {
+            if ((r2 = launch_projection(ctx, &dA, p, pk[g], algo, reinterpret_cast<float*>(base + o_y[g]), p, cs)) !=
+                RP_OK)
                 return r2;
-            }
         }
         if (grouped_stages) {
             // Algorithm 1 lines 2-4 for every problem at once (power scheme:

@@ -37,6 +37,36 @@ def test_project_grouped_elementwise_bound():
         assert np.all(np.abs(y - ref) <= bound), (j, m, n, r)
 
 
+def test_project_grouped_general_matches_single():
+    """Problems off the 16-byte path go out in grouped launches of the general
+    kernel (odd and 2 mod 4 row lengths, an unaligned strided view, a caller
+    pre-scale 2^s, both column widths): every Y bit-identical to the same
+    problem's single call (same tile, same arithmetic) and, for s = 0, within
+    the elementwise bound of the split product."""
+    rng = np.random.default_rng(21)
+    big = rng.standard_normal((700, 1301)).astype(np.float32)
+    mats = [big[:, 3:1003], rng.standard_normal((513, 999)).astype(np.float32),
+            rng.standard_normal((1500, 333)).astype(np.float32), rng.standard_normal((257, 2050)).astype(np.float32),
+            rng.standard_normal((300, 512)).astype(np.float32)]
+    rs, exps = [150, 64, 300, 17, 100], [0, 0, 0, 0, 5]
+    announce(f"grouped general-kernel projections {[a.shape for a in mats]} r {rs} s {exps}")
+    dbig = dev(big)
+    dmats = [dbig[:, 3:1003]] + [dev(a) for a in mats[1:]]
+    probs = [(a, r, 4, j, s) for j, (a, r, s) in enumerate(zip(dmats, rs, exps))]
+    ys = rp().rp_project_grouped(probs)
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, (a, da, r, s) in enumerate(zip(mats, dmats, rs, exps)):
+        one = host(rp().rp_project(da, r, seed=4, stream_id=j, a_scale_exp=s))
+        y = host(ys[j])
+        assert np.array_equal(y, one), j
+        if s == 0:
+            n = a.shape[1]
+            om = omega.omega_f16(4, j, n, r)
+            ref = project.project_f64(a.astype(np.float64), om)
+            bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, om)
+            assert np.all(np.abs(y.astype(np.float64) - ref) <= bound), j
+
+
 def _planted_batch(count, seed, lo, hi, kmin, kmax):
     """m, n log-uniform in [lo, hi], planted rank k, sigma_i =
     10^(-3 (i-1)/(k-1)), Haar factors, noiseless; p = k + max(10, ceil(k/4))."""
