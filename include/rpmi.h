@@ -427,6 +427,27 @@ rp_status rp_split_f16(rp_ctx ctx, const float* x, int64_t count,
  */
 rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* out);
 
+/*
+ * Autotuner cache of the grouped projections (the batching of Sec. 5's
+ * many-problem runs and of Algorithm 2's per-mode projections): the first
+ * rsvd_batched call on a problem-shape signature times the grouped launch
+ * at several contraction-split scales (the CU share each problem's split is
+ * planned for) and keeps the fastest per context.  The cache persists:
+ *   - rp_tuning_save writes every entry to `path` as text, one line
+ *     "<signature hex> <scale>" per entry (replacing the file);
+ *   - rp_tuning_load adds the entries of such a file (later lines win);
+ *     a line that does not parse stops the load with RP_ERR_INVALID_ARG
+ *     (entries read before it are kept); a missing file is RP_ERR_INVALID_ARG;
+ *   - rp_tuning_count gives the number of entries.
+ * If the environment variable RPMI_TUNING_FILE names a file when rp_create
+ * runs, the context loads it (a missing or bad file is ignored) and writes
+ * it back after each new tuning.  Signatures include the device's compute
+ * unit count, so a file from another chip model matches nothing.  Host only.
+ */
+rp_status rp_tuning_save(rp_ctx ctx, const char* path);
+rp_status rp_tuning_load(rp_ctx ctx, const char* path);
+rp_status rp_tuning_count(rp_ctx ctx, int64_t* entries);
+
 #ifdef __cplusplus
 }
 #endif

@@ -89,6 +89,9 @@ def lib():
         "rp_project_grouped": [vp, i32, vp, i32, vp],
         "rp_omega_generate_e4m3": [vp, u64, u32, i64, i64, vp, i64, vp, vp],
         "rsvd_batched": [vp, i32, vp, i32, u64, i32, vp],
+        "rp_tuning_save": [vp, ctypes.c_char_p],
+        "rp_tuning_load": [vp, ctypes.c_char_p],
+        "rp_tuning_count": [vp, ctypes.POINTER(i64)],
         "rpmi_build_f16_thresholds": [vp, i32],
         "rpmi_build_guide": [vp, i32, vp, i32],
     }
@@ -392,6 +395,25 @@ def rsvd_batched(mats, ks, oversamples, power_iters=0, seed=0, omega_type="f16",
         arr[i].VT, arr[i].ldvt = _ptr(vt), vt.stride(0)
     _check(ctx.handle, lib().rsvd_batched(ctx.handle, n, arr, power_iters, seed, OMEGA_TYPES[omega_type], _stream()))
     return outs
+
+
+def rp_tuning_save(path, ctx=None):
+    """Write the context's autotuner entries to ``path``."""
+    ctx = ctx or default_context()
+    _check(ctx.handle, lib().rp_tuning_save(ctx.handle, os.fsencode(path)))
+
+
+def rp_tuning_load(path, ctx=None):
+    """Add the autotuner entries of ``path`` to the context."""
+    ctx = ctx or default_context()
+    _check(ctx.handle, lib().rp_tuning_load(ctx.handle, os.fsencode(path)))
+
+
+def rp_tuning_count(ctx=None):
+    ctx = ctx or default_context()
+    out = ctypes.c_int64(0)
+    _check(ctx.handle, lib().rp_tuning_count(ctx.handle, ctypes.byref(out)))
+    return out.value
 
 
 def rp_get_device_status(clear=True, ctx=None):

@@ -48,65 +48,128 @@ __global__ __launch_bounds__(256) void gemm_acc64_group_kernel(const GemmJob* __
                             ti * GT, tj * GT);
 }
 
+// G = Y^T Y per job: block b of the job is (kz, t) with t an upper-triangle
+// 64 x 64 tile (ti <= tj, row by row); the tile's product over rows
+// [kz kchunk, (kz + 1) kchunk) goes to partial kz (or straight to G when the
+// job is not split), mirrored into the lower triangle.
+template <class T>
+__global__ __launch_bounds__(256) void gram_group_kernel(const GramJob* __restrict__ jobs,
+                                                         const int64_t* __restrict__ starts, int count) {
+    const int64_t blk = blockIdx.x;
+    const GramJob J = jobs[find_job(starts, count, blk)];
+    const int64_t local = blk - J.start;
+    const int kz = (int)(local / J.tiles);
+    int t = (int)(local - (int64_t)kz * J.tiles);
+    const int tt = (int)((J.p + GT - 1) / GT);
+    int ti = 0;
+    while (t >= tt - ti) {
+        t -= tt - ti;
+        ++ti;
+    }
+    const int tj = ti + t;
+    const int64_t k0 = kz * J.kchunk;
+    const int64_t klen = J.R - k0 < J.kchunk ? J.R - k0 : J.kchunk;
+    const T* y = static_cast<const T*>(J.y) + k0 * J.ldy;
+    double* c = J.ksplit > 1 ? J.part + (int64_t)kz * J.p * J.p : J.G;
+    gemm64_tile<T, T, double, true>(J.p, J.p, klen, 1.0, y, 1, J.ldy, y, J.ldy, 1, 0.0, c, J.p, 1, ti * GT, tj * GT);
+}
+
+// G = sum of the job's partials, in order (kSumBlocks workgroups per job)
+constexpr int kSumBlocks = 16;
+__global__ __launch_bounds__(256) void gram_sum_group_kernel(const GramJob* __restrict__ jobs) {
+    const GramJob J = jobs[blockIdx.x];
+    if (J.ksplit <= 1) return;
+    const int64_t pp = J.p * J.p;
+    for (int64_t e = blockIdx.y * 256 + threadIdx.x; e < pp; e += 256 * kSumBlocks) {
+        double acc = 0.0;
+        for (int z = 0; z < J.ksplit; ++z) acc += J.part[z * pp + e];
+        J.G[e] = acc;
+    }
+}
+
 // Packed lower triangle: element (i, l), l <= i, at i (i + 1) / 2 + l.
 __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 
-__global__ __launch_bounds__(256) void chol_inv_group_kernel(const CholJob* __restrict__ jobs, unsigned int* status) {
+// Pivot of a Cholesky step; a non-positive (or NaN) pivot is reported by the
+// caller and replaced by |v| (1 if zero) so that the factorization finishes.
+__device__ __forceinline__ double chol_pivot(double v) { return v > 0.0 ? v : (fabs(v) > 0.0 ? fabs(v) : 1.0); }
+
+constexpr int kCholThreads = 1024;
+
+// One workgroup per problem, everything in LDS: the packed lower triangle T
+// (p (p + 1) / 2 doubles) and two column buffers of p doubles.
+//  * Cholesky, right-looking without scaled columns: step j subtracts
+//    T_ij T_lj / T_jj from every T_il, j < l <= i (column j itself is not
+//    written, so one barrier per step); afterwards d_j = sqrt(T_jj) and
+//    L_ij = T_ij / d_j.
+//  * X = L^-1 in place, last column first: from X L = I,
+//    X_ij = -(sum_{l=j+1..i} X_il L_lj) / L_jj for i > j, X_jj = 1 / L_jj;
+//    column j of L is copied to a buffer one step ahead (double buffer, one
+//    barrier per step); four lanes share a row's sum.
+__global__ __launch_bounds__(kCholThreads) void chol_inv_group_kernel(const CholJob* __restrict__ jobs,
+                                                                      unsigned int* status) {
     extern __shared__ double T[];
     const CholJob J = jobs[blockIdx.x];
     const int p = J.p, tid = threadIdx.x;
-    __shared__ double dsh;
-    for (int e = tid; e < p * (p + 1) / 2; e += 256) {
-        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (tri(i, 0) > e) --i;
-        while (tri(i + 1, 0) <= e) ++i;
-        const int l = e - tri(i, 0);
-        T[e] = J.G[(int64_t)i * p + l];
-    }
+    const int np = p * (p + 1) / 2;
+    double* cb0 = T + np;
+    double* cb1 = cb0 + p;
+    for (int i = tid >> 5; i < p; i += kCholThreads / 32)
+        for (int l = tid & 31; l <= i; l += 32) T[tri(i, l)] = J.G[(int64_t)i * p + l];
     __syncthreads();
-    // right-looking Cholesky, one column per step
+    const int tx = tid & 31, ty = tid >> 5;
     for (int j = 0; j < p; ++j) {
-        if (tid == 0) {
-            double v = T[tri(j, j)];
-            if (!(v > 0.0)) {
-                atomicOr(status, kStatusNotSpd);
-                v = fabs(v) > 0.0 ? fabs(v) : 1.0;
-            }
-            dsh = sqrt(v);
-            T[tri(j, j)] = dsh;
-        }
-        __syncthreads();
-        const double d = dsh;
-        for (int i = j + 1 + tid; i < p; i += 256) T[tri(i, j)] /= d;
-        __syncthreads();
-        const int w = p - j - 1;
-        for (int e = tid; e < w * w; e += 256) {
-            const int i = j + 1 + e / w, l = j + 1 + e % w;
-            if (l <= i) T[tri(i, l)] -= T[tri(i, j)] * T[tri(l, j)];
+        const double v = T[tri(j, j)];
+        if (tid == 0 && !(v > 0.0)) atomicOr(status, kStatusNotSpd);
+        const double rv = 1.0 / chol_pivot(v);
+        for (int i = j + 1 + ty; i < p; i += kCholThreads / 32) {
+            const double a = T[tri(i, j)] * rv;
+            for (int l = j + 1 + tx; l <= i; l += 32) T[tri(i, l)] -= a * T[tri(l, j)];
         }
         __syncthreads();
     }
-    // L (zero above the diagonal) to L_out
-    for (int e = tid; e < p * p; e += 256) {
+    for (int j = tid; j < p; j += kCholThreads) cb0[j] = sqrt(chol_pivot(T[tri(j, j)]));
+    __syncthreads();
+    for (int i = ty; i < p; i += kCholThreads / 32)
+        for (int l = tx; l <= i; l += 32) T[tri(i, l)] = l == i ? cb0[i] : T[tri(i, l)] / cb0[l];
+    __syncthreads();
+    for (int e = tid; e < p * p; e += kCholThreads) {
         const int i = e / p, l = e % p;
         J.L[e] = l <= i ? T[tri(i, l)] : 0.0;
     }
-    // X = L^-1: thread c solves L x = e_c for column c, top to bottom
-    for (int cidx = tid; cidx < p; cidx += 256) {
-        for (int i = 0; i < cidx; ++i) J.X[(int64_t)i * p + cidx] = 0.0;
-        for (int i = cidx; i < p; ++i) {
-            double s = i == cidx ? 1.0 : 0.0;
-            for (int l = cidx; l < i; ++l) s -= T[tri(i, l)] * J.X[(int64_t)l * p + cidx];
-            J.X[(int64_t)i * p + cidx] = s / T[tri(i, i)];
-        }
+    // inverse: cb holds column j of L (rows j..p-1) while column j is solved
+    for (int l = p - 1 + tid; l < p; l += kCholThreads) cb0[l] = T[tri(l, p - 1)];
+    __syncthreads();
+    const int q = tid & 3, row = tid >> 2;
+    for (int j = p - 1; j >= 0; --j) {
+        double* cb = ((p - 1 - j) & 1) ? cb1 : cb0;
+        double* nb = ((p - 1 - j) & 1) ? cb0 : cb1;
+        if (j > 0)
+            for (int l = j - 1 + tid; l < p; l += kCholThreads) nb[l] = T[tri(l, j - 1)];
+        const int i = j + 1 + row;
+        double acc = 0.0;
+        if (i < p)
+            for (int l = j + 1 + q; l <= i; l += 4) acc += T[tri(i, l)] * cb[l];
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        if (i < p && q == 0) T[tri(i, j)] = -acc / cb[j];
+        if (tid == 0) T[tri(j, j)] = 1.0 / cb[j];
+        __syncthreads();
+    }
+    for (int e = tid; e < p * p; e += kCholThreads) {
+        const int i = e / p, l = e % p;
+        J.X[e] = l <= i ? T[tri(i, l)] : 0.0;
     }
 }
 
 // C (N x P) = A^T Q for A (K x N, lda) and Q (K x P, ldq) on
-// v_mfma_f32_16x16x4f32: the tiling of gemm_tn_f32 (a wave owns 64 x 64 of
-// C as 4 x 4 MFMA tiles with rows and columns permuted so that lane c reads
-// four consecutive elements of a row of A and of Q); VEC: those four are one
-// 16-byte load (lda, ldq, ldc multiples of 4 and 16-byte aligned bases).
+// v_mfma_f32_16x16x4f32: a wave owns 64 x 64 of C as 4 x 4 MFMA tiles whose
+// rows and columns are permuted to suit the loads.  VEC (lda, ldq, ldc
+// multiples of 4, 16-byte aligned bases): lane c reads four consecutive
+// elements of a row of A and of Q with one 16-byte load (tile a, MFMA row c
+// is C row i0 + 4c + a).  Otherwise lane c reads column i0 + 16a + c, so the
+// 16 lanes of a row read 64 consecutive bytes with each 4-byte load (MFMA row
+// c of tile a is C row i0 + 16a + c).
 template <bool VEC>
 __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
                                                                 const int64_t* __restrict__ starts, int count) {
@@ -114,7 +177,13 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
     const int64_t blk = blockIdx.x;
     const TnJob J = jobs[find_job(starts, count, blk)];
     const int64_t local = blk - J.start;
-    const int64_t bx = local % J.tiles_x, by = local / J.tiles_x;
+    const int64_t per_k = J.tiles_x * J.tiles_y;
+    const int kz = (int)(local / per_k);
+    const int64_t rest = local - kz * per_k;
+    const int64_t bx = rest % J.tiles_x, by = rest / J.tiles_x;
+    const int64_t kbeg = kz * J.kchunk, kend = J.K < kbeg + J.kchunk ? J.K : kbeg + J.kchunk;
+    float* const Cout = J.ksplit > 1 ? J.part + kz * J.N * J.P : J.C;
+    const int64_t ldc = J.ksplit > 1 ? J.P : J.ldc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int64_t i0 = (by * 4 + wave) * 64, j0 = bx * 64;
@@ -125,21 +194,26 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    auto load4 = [](const float* row, int64_t col, int64_t lim, bool full) -> f4 {
-        if (VEC && full) return *reinterpret_cast<const f4*>(row + col);
+    auto load4 = [&](const float* row, int64_t base, int64_t lim, bool full) -> f4 {
         f4 v;
+        if constexpr (VEC) {
+            if (full) return *reinterpret_cast<const f4*>(row + base + 4 * c);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = col + e < lim ? row[col + e] : 0.0f;
+            for (int e = 0; e < 4; ++e) v[e] = base + 4 * c + e < lim ? row[base + 4 * c + e] : 0.0f;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = base + 16 * e + c < lim ? row[base + 16 * e + c] : 0.0f;
+        }
         return v;
     };
-    for (int64_t k0 = 0; k0 < J.K; k0 += 16) {
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
         f4 av[4], qv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t k = k0 + 4 * u + g;
-            const bool in = k < J.K;
-            av[u] = in ? load4(J.A + k * J.lda, ia, J.N, a_full) : f4{0.f, 0.f, 0.f, 0.f};
-            qv[u] = in ? load4(J.Q + k * J.ldq, jq, J.P, q_full) : f4{0.f, 0.f, 0.f, 0.f};
+            const bool in = k < kend;
+            av[u] = in ? load4(J.A + k * J.lda, i0, J.N, a_full) : f4{0.f, 0.f, 0.f, 0.f};
+            qv[u] = in ? load4(J.Q + k * J.ldq, j0, J.P, q_full) : f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -149,21 +223,36 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
     }
+    // lane (c, g) holds D[4g + e][c] of every MFMA tile
+    if constexpr (VEC) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t i = i0 + 4 * (4 * g + e) + a;
-            if (i >= J.N) continue;
-            float* crow = J.C + i * J.ldc;
-            if (VEC && q_full) {
-                *reinterpret_cast<f4*>(crow + jq) = f4{acc[a][0][e], acc[a][1][e], acc[a][2][e], acc[a][3][e]};
-            } else {
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = i0 + 4 * (4 * g + e) + a;
+                if (i >= J.N) continue;
+                float* crow = Cout + i * ldc;
+                if (q_full) {
+                    *reinterpret_cast<f4*>(crow + jq) = f4{acc[a][0][e], acc[a][1][e], acc[a][2][e], acc[a][3][e]};
+                } else {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (jq + b < J.P) crow[jq + b] = acc[a][b][e];
+                }
+            }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = i0 + 16 * a + 4 * g + e;
+                if (i >= J.N) continue;
+                float* crow = Cout + i * ldc;
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    if (jq + b < J.P) crow[jq + b] = acc[a][b][e];
+                    if (j0 + 16 * b + c < J.P) crow[j0 + 16 * b + c] = acc[a][b][e];
             }
-        }
+    }
 }
 
 // sigma_j = |w_j| (column norms of W, row-major n x n); rank by sigma
@@ -232,22 +321,55 @@ template hipError_t gemm_acc64_group<double, double, float>(const GemmJob*, cons
                                                             hipStream_t);
 template hipError_t gemm_acc64_group<float, double, float>(const GemmJob*, const int64_t*, int, int64_t, hipStream_t);
 
+int gram_group_tiles(int64_t p) {
+    const int tt = (int)((p + GT - 1) / GT);
+    return tt * (tt + 1) / 2;
+}
+
+template <class T>
+hipError_t gram_group(const GramJob* jobs, const int64_t* starts, int count, int64_t blocks, bool any_split,
+                      hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gram_group_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !any_split) return e;
+    hipLaunchKernelGGL(gram_sum_group_kernel, dim3((unsigned)count, kSumBlocks), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+template hipError_t gram_group<float>(const GramJob*, const int64_t*, int, int64_t, bool, hipStream_t);
+template hipError_t gram_group<double>(const GramJob*, const int64_t*, int, int64_t, bool, hipStream_t);
+
 hipError_t chol_inv_group(const CholJob* jobs, int count, int max_p, unsigned int* status, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (max_p > kCholGroupMaxP) return hipErrorInvalidValue;
-    const size_t lds = (size_t)max_p * (max_p + 1) / 2 * sizeof(double);
+    const size_t lds = ((size_t)max_p * (max_p + 1) / 2 + 2 * (size_t)max_p) * sizeof(double);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_group_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(chol_inv_group_kernel, dim3((unsigned)count), dim3(256), lds, s, jobs, status);
+    hipLaunchKernelGGL(chol_inv_group_kernel, dim3((unsigned)count), dim3(kCholThreads), lds, s, jobs, status);
     return hipGetLastError();
 }
 
 int64_t tn_group_tiles_x(int64_t P) { return (P + 63) / 64; }
 int64_t tn_group_tiles(int64_t N, int64_t P) { return ((P + 63) / 64) * ((N + 255) / 256); }
 
+// C = sum of the job's partials, in order (kSumBlocks workgroups per job)
+__global__ __launch_bounds__(256) void tn_sum_group_kernel(const TnJob* __restrict__ jobs) {
+    const TnJob J = jobs[blockIdx.x];
+    if (J.ksplit <= 1) return;
+    const int64_t np = J.N * J.P;
+    for (int64_t e = blockIdx.y * 256 + threadIdx.x; e < np; e += 256 * kSumBlocks) {
+        float acc = 0.0f;
+        for (int z = 0; z < J.ksplit; ++z) acc += J.part[z * np + e];
+        const int64_t i = e / J.P, j = e - i * J.P;
+        J.C[i * J.ldc + j] = acc;
+    }
+}
+
 hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
-                             hipStream_t s) {
+                             bool any_split, hipStream_t s) {
     if (count <= 0 || blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     if (vec)
@@ -256,6 +378,9 @@ hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count
     else
         hipLaunchKernelGGL(gemm_tn_f32_group_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
                            count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !any_split) return e;
+    hipLaunchKernelGGL(tn_sum_group_kernel, dim3((unsigned)count, kSumBlocks), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 

@@ -274,12 +274,28 @@ __global__ void colmax_init_kernel(unsigned int* cmax, int64_t r, float* scale_o
 }
 
 // max |w| per column as the bit pattern of a non-negative float (the order of
-// non-negative floats is the order of their patterns)
-__global__ void colmax_kernel(const float* w, int64_t n, int64_t r, int64_t ldw, unsigned int* cmax) {
-    const int64_t total = n * r;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q / r, j = q - i * r;
-        atomicMax(&cmax[j], __float_as_uint(fabsf(w[i * ldw + j])));
+// non-negative floats is the order of their patterns).  A block owns 64
+// columns (blockIdx.x) and a strided share of the rows (blockIdx.y): each
+// thread keeps the maximum of its rows, the block's four row lanes meet in
+// LDS, and one atomic per column and block publishes it.
+constexpr int kColmaxRowBlocks = 64;
+__global__ __launch_bounds__(256) void colmax_kernel(const float* w, int64_t n, int64_t r, int64_t ldw,
+                                                     unsigned int* cmax) {
+    __shared__ unsigned int part[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+    unsigned int mx = 0u;
+    if (j < r)
+        for (int64_t i = (int64_t)blockIdx.y * 4 + ty; i < n; i += (int64_t)gridDim.y * 4) {
+            const unsigned int v = __float_as_uint(fabsf(w[i * ldw + j]));
+            mx = v > mx ? v : mx;
+        }
+    part[ty][tx] = mx;
+    __syncthreads();
+    if (ty == 0 && j < r) {
+#pragma unroll
+        for (int t = 1; t < 4; ++t) mx = part[t][tx] > mx ? part[t][tx] : mx;
+        atomicMax(&cmax[j], mx);
     }
 }
 
@@ -339,7 +355,9 @@ hipError_t launch_omega_e4m3(const OmegaTables& t, uint64_t seed, uint32_t strea
                        n == 0 ? scale : (float*)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(colmax_kernel, dim3(grid_for(n * r, 256)), dim3(256), 0, s, w32, n, r, r, cmax);
+    const int64_t rb = (n + 3) / 4 < kColmaxRowBlocks ? (n + 3) / 4 : kColmaxRowBlocks;
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)((r + 63) / 64), (unsigned)rb), dim3(256), 0, s, w32, n, r, r,
+                       cmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(e4m3_quant_kernel, dim3(grid_for(n * r, 256)), dim3(256), 0, s, w32, n, r, r, cmax, codes, ldc,
                        f16, ldf, scale);

@@ -2,6 +2,7 @@
 // validation, context state (Omega tables, status word, workspace) and
 // dispatch to the kernels.  No C++ exception crosses the ABI.
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -53,6 +54,7 @@ struct rp_ctx_s {
     char* graph_aux = nullptr;                // job tables of the grouped stages read by the graph
     size_t graph_aux_bytes = 0;
     std::unordered_map<uint64_t, double> tuned_scale;
+    std::string tuning_file;              // RPMI_TUNING_FILE at creation ("" if unset)
     // generated Omega kept in device memory, keyed by what defines its bits
     // (seed, stream_id, n, r, type) and by the fragment format (algorithm);
     // least recently used entries are freed beyond kOmegaCacheBytes
@@ -158,6 +160,40 @@ const char* rp_last_error(rp_ctx ctx) {
     return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
 }
 
+namespace {
+
+rp_status tuning_load(rp_ctx ctx, const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(ctx, RP_ERR_INVALID_ARG, "cannot open tuning file %s", path);
+    char line[256];
+    int lineno = 0;
+    rp_status st = RP_OK;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        unsigned long long key = 0;
+        double scale = 0.0;
+        char extra = 0;
+        if (line[0] == '\n' || line[0] == '\0') continue;
+        if (sscanf(line, "%llx %lf %c", &key, &scale, &extra) != 2 || !(scale > 0.0) || scale > 64.0) {
+            st = fail(ctx, RP_ERR_INVALID_ARG, "tuning file %s line %d does not parse", path, lineno);
+            break;
+        }
+        ctx->tuned_scale[(uint64_t)key] = scale;
+    }
+    fclose(f);
+    return st;
+}
+
+rp_status tuning_save(rp_ctx ctx, const char* path) {
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(ctx, RP_ERR_INVALID_ARG, "cannot write tuning file %s", path);
+    for (const auto& e : ctx->tuned_scale) fprintf(f, "%016llx %.17g\n", (unsigned long long)e.first, e.second);
+    const bool ok = fclose(f) == 0;
+    return ok ? RP_OK : fail(ctx, RP_ERR_INVALID_ARG, "writing tuning file %s failed", path);
+}
+
+}  // namespace
+
 rp_status rp_create(rp_ctx* out, int device) {
     if (!out) return fail(nullptr, RP_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -209,7 +245,31 @@ rp_status rp_create(rp_ctx* out, int device) {
             return cleanup(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
         ctx->noalloc_scratch = static_cast<unsigned char*>(p);
     }
+    if (const char* tf = getenv("RPMI_TUNING_FILE")) {
+        if (tf[0]) {
+            ctx->tuning_file = tf;
+            (void)tuning_load(ctx, tf);
+            ctx->last_error.clear();
+        }
+    }
     *out = ctx;
+    return RP_OK;
+}
+
+
+rp_status rp_tuning_save(rp_ctx ctx, const char* path) {
+    if (!ctx || !path) return fail(ctx, RP_ERR_INVALID_ARG, "ctx or path is NULL");
+    return tuning_save(ctx, path);
+}
+
+rp_status rp_tuning_load(rp_ctx ctx, const char* path) {
+    if (!ctx || !path) return fail(ctx, RP_ERR_INVALID_ARG, "ctx or path is NULL");
+    return tuning_load(ctx, path);
+}
+
+rp_status rp_tuning_count(rp_ctx ctx, int64_t* entries) {
+    if (!ctx || !entries) return fail(ctx, RP_ERR_INVALID_ARG, "ctx or entries is NULL");
+    *entries = (int64_t)ctx->tuned_scale.size();
     return RP_OK;
 }
 
@@ -1149,39 +1209,113 @@ struct CholStage {
     int count = 0, max_p = 0;
 };
 
+// Grouped Grams: each job's rows go out in ksplit chunks of at least 512
+// rows (at most 16 chunks), so that a tall problem spreads over several
+// workgroups per tile; the partial sums need ksplit p^2 doubles per job.
+struct GramStage {
+    size_t jobs = 0, starts = 0;
+    int count = 0;
+    int64_t blocks = 0;
+    bool any_split = false;
+};
+
+int gram_split(int64_t R) {
+    const int64_t s = R / 512;
+    return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
+}
+
+size_t gram_part_bytes(const std::vector<int64_t>& rows, const std::vector<int64_t>& ps) {
+    size_t b = 0;
+    for (size_t i = 0; i < rows.size(); ++i) {
+        const int s = gram_split(rows[i]);
+        if (s > 1) b += ((size_t)s * ps[i] * ps[i] * sizeof(double) + 255) & ~size_t(255);
+    }
+    return b;
+}
+
+// jobs: (Y, R rows, p, G); part: gram_part_bytes of these rows
+GramStage add_gram_stage(AuxImage& im, std::vector<rpmi::GramJob> jobs, char* part) {
+    GramStage st;
+    std::vector<int64_t> starts(jobs.size());
+    int64_t b = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        rpmi::GramJob& j = jobs[i];
+        const int s = gram_split(j.R);
+        j.kchunk = s > 1 ? (((j.R + s - 1) / s + 15) / 16) * 16 : (j.R > 0 ? j.R : 1);
+        j.ksplit = (int)((j.R + j.kchunk - 1) / j.kchunk);
+        j.ksplit = j.ksplit < 1 ? 1 : j.ksplit;
+        j.part = nullptr;
+        if (j.ksplit > 1) {
+            j.part = reinterpret_cast<double*>(part);
+            part += ((size_t)s * j.p * j.p * sizeof(double) + 255) & ~size_t(255);
+            st.any_split = true;
+        }
+        j.tiles = rpmi::gram_group_tiles(j.p);
+        j.start = b;
+        starts[i] = b;
+        b += (int64_t)j.tiles * j.ksplit;
+    }
+    st.count = (int)jobs.size();
+    st.blocks = b;
+    if (!jobs.empty()) {
+        st.jobs = im.add(jobs.data(), jobs.size() * sizeof(rpmi::GramJob));
+        st.starts = im.add(starts.data(), starts.size() * sizeof(int64_t));
+    }
+    return st;
+}
+
+rpmi::GramJob gram_job(const void* y, int64_t R, int64_t p, double* G) {
+    rpmi::GramJob j{};
+    j.y = y;
+    j.ldy = p;
+    j.R = R;
+    j.p = p;
+    j.G = G;
+    return j;
+}
+
+template <class T>
+hipError_t run_gram_stage(const GramStage& st, char* aux, hipStream_t s) {
+    return rpmi::gram_group<T>(reinterpret_cast<const rpmi::GramJob*>(aux + st.jobs),
+                               reinterpret_cast<const int64_t*>(aux + st.starts), st.count, st.blocks, st.any_split, s);
+}
+
 // CholeskyQR2 of every problem's Y (rows R_g x p_g, FP32, ld p_g) into Q
 // (FP32, ld p_g), with scratch from its RsvdScratch; with_m: also M = L1 L2
 // (into MW), the lower factor R^T of the triangular factor R.
 struct CholQr2Group {
-    GemmStage gram1, qd, gram2, q, m;
+    GramStage gram1, gram2;
+    GemmStage qd, q, m;
     CholStage chol1, chol2;
     bool with_m = false;
 };
 
 CholQr2Group build_cholqr2_group(AuxImage& im, const std::vector<int64_t>& rows, const std::vector<float*>& Y,
-                                 const std::vector<float*>& Q, const std::vector<RsvdScratch>& ws, bool with_m) {
+                                 const std::vector<float*>& Q, const std::vector<RsvdScratch>& ws, bool with_m,
+                                 char* gram_part) {
     const size_t n = ws.size();
-    std::vector<rpmi::GemmJob> g1, qd, g2, qq, mm;
+    std::vector<rpmi::GemmJob> qd, qq, mm;
+    std::vector<rpmi::GramJob> g1, g2;
     std::vector<rpmi::CholJob> c1, c2;
     CholQr2Group G;
     G.with_m = with_m;
     for (size_t i = 0; i < n; ++i) {
         const RsvdScratch& w = ws[i];
         const int64_t p = w.p, R = rows[i];
-        g1.push_back(gemm_job(p, p, R, Y[i], 1, p, Y[i], p, 1, w.G, p, 1));
+        g1.push_back(gram_job(Y[i], R, p, w.G));
         c1.push_back(rpmi::CholJob{w.G, with_m ? w.L1 : w.G, w.X, (int)p});
         qd.push_back(gemm_job(R, p, p, Y[i], p, 1, w.X, 1, p, w.Qd, p, 1));
-        g2.push_back(gemm_job(p, p, R, w.Qd, 1, p, w.Qd, p, 1, w.G, p, 1));
+        g2.push_back(gram_job(w.Qd, R, p, w.G));
         c2.push_back(rpmi::CholJob{w.G, w.G, w.X, (int)p});
         qq.push_back(gemm_job(R, p, p, w.Qd, p, 1, w.X, 1, p, Q[i], p, 1));
         if (with_m) mm.push_back(gemm_job(p, p, p, w.L1, p, 1, w.G, p, 1, w.MW, p, 1));
         G.chol1.max_p = G.chol2.max_p = (int)p > G.chol1.max_p ? (int)p : G.chol1.max_p;
     }
-    G.gram1 = add_gemm_stage(im, g1);
+    G.gram1 = add_gram_stage(im, g1, gram_part);
     G.chol1.jobs = im.add(c1.data(), n * sizeof(rpmi::CholJob));
     G.chol1.count = (int)n;
     G.qd = add_gemm_stage(im, qd);
-    G.gram2 = add_gemm_stage(im, g2);
+    G.gram2 = add_gram_stage(im, g2, gram_part);
     G.chol2.jobs = im.add(c2.data(), n * sizeof(rpmi::CholJob));
     G.chol2.count = (int)n;
     G.q = add_gemm_stage(im, qq);
@@ -1197,11 +1331,11 @@ hipError_t run_gemm_stage(const GemmStage& st, char* aux, hipStream_t s) {
 }
 
 rp_status run_cholqr2_group(rp_ctx ctx, const CholQr2Group& G, char* aux, hipStream_t s) {
-    RP_HIP(ctx, (run_gemm_stage<float, float, double>(G.gram1, aux, s)));
+    RP_HIP(ctx, run_gram_stage<float>(G.gram1, aux, s));
     RP_HIP(ctx, rpmi::chol_inv_group(reinterpret_cast<const rpmi::CholJob*>(aux + G.chol1.jobs), G.chol1.count,
                                      G.chol1.max_p, ctx->d_status, s));
     RP_HIP(ctx, (run_gemm_stage<float, double, double>(G.qd, aux, s)));
-    RP_HIP(ctx, (run_gemm_stage<double, double, double>(G.gram2, aux, s)));
+    RP_HIP(ctx, run_gram_stage<double>(G.gram2, aux, s));
     RP_HIP(ctx, rpmi::chol_inv_group(reinterpret_cast<const rpmi::CholJob*>(aux + G.chol2.jobs), G.chol2.count,
                                      G.chol2.max_p, ctx->d_status, s));
     RP_HIP(ctx, (run_gemm_stage<double, double, float>(G.q, aux, s)));
@@ -1215,9 +1349,31 @@ struct TnGroup {
     size_t jobs[2] = {0, 0}, starts[2] = {0, 0};
     int count[2] = {0, 0};
     int64_t blocks[2] = {0, 0};
+    bool any_split[2] = {false, false};
 };
 
-TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::vector<RsvdScratch>& ws) {
+// Contraction split of a grouped A^T Q with few output tiles: enough chunks
+// (of at least 1024 rows, at most 8) to give the problem about 24 workgroups.
+int tn_split(int64_t K, int64_t N, int64_t P) {
+    const int64_t tiles = rpmi::tn_group_tiles(N, P);
+    int64_t s = (24 + tiles - 1) / tiles;
+    const int64_t kmax = K / 1024;
+    s = s > kmax ? kmax : s;
+    s = s > 8 ? 8 : s;
+    return (int)(s < 1 ? 1 : s);
+}
+
+size_t tn_part_bytes(const rp_rsvd_problem* probs, int32_t count) {
+    size_t b = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const int64_t p = probs[g].k + probs[g].oversample;
+        const int s = tn_split(probs[g].m, probs[g].n, p);
+        if (s > 1) b += ((size_t)s * probs[g].n * p * sizeof(float) + 255) & ~size_t(255);
+    }
+    return b;
+}
+
+TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::vector<RsvdScratch>& ws, char* part) {
     TnGroup T;
     std::vector<rpmi::TnJob> jobs[2];
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
@@ -1227,6 +1383,15 @@ TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::ve
         rpmi::TnJob j{};
         j.N = q.n; j.P = w.p; j.K = q.m;
         j.A = q.A; j.lda = q.lda; j.Q = w.Q; j.ldq = w.p; j.C = w.Z; j.ldc = w.p;
+        const int sp = tn_split(q.m, q.n, w.p);
+        j.kchunk = sp > 1 ? (((q.m + sp - 1) / sp + 15) / 16) * 16 : (q.m > 0 ? q.m : 1);
+        j.ksplit = (int)((q.m + j.kchunk - 1) / j.kchunk);
+        j.ksplit = j.ksplit < 1 ? 1 : j.ksplit;
+        j.part = nullptr;
+        if (j.ksplit > 1) {
+            j.part = reinterpret_cast<float*>(part);
+            part += ((size_t)sp * q.n * w.p * sizeof(float) + 255) & ~size_t(255);
+        }
         const bool vec = q.lda % 4 == 0 && w.p % 4 == 0 && al(q.A) && al(w.Q) && al(w.Z);
         jobs[vec ? 1 : 0].push_back(j);
     }
@@ -1235,9 +1400,11 @@ TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::ve
         int64_t b = 0;
         for (size_t i = 0; i < jobs[v].size(); ++i) {
             jobs[v][i].tiles_x = rpmi::tn_group_tiles_x(jobs[v][i].P);
+            jobs[v][i].tiles_y = (jobs[v][i].N + 255) / 256;
             jobs[v][i].start = b;
             starts[i] = b;
-            b += rpmi::tn_group_tiles(jobs[v][i].N, jobs[v][i].P);
+            b += rpmi::tn_group_tiles(jobs[v][i].N, jobs[v][i].P) * jobs[v][i].ksplit;
+            if (jobs[v][i].ksplit > 1) T.any_split[v] = true;
         }
         T.count[v] = (int)jobs[v].size();
         T.blocks[v] = b;
@@ -1254,7 +1421,7 @@ rp_status run_tn_group(rp_ctx ctx, const TnGroup& T, char* aux, hipStream_t s) {
         if (T.count[v] > 0)
             RP_HIP(ctx, rpmi::gemm_tn_f32_group(reinterpret_cast<const rpmi::TnJob*>(aux + T.jobs[v]),
                                                 reinterpret_cast<const int64_t*>(aux + T.starts[v]), T.count[v],
-                                                T.blocks[v], v == 1, s));
+                                                T.blocks[v], v == 1, T.any_split[v], s));
     return RP_OK;
 }
 
@@ -1494,6 +1661,19 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     std::vector<size_t> o_ws(count);
     for (int32_t g = 0; g < count; ++g)
         o_ws[g] = ws[g].layout(ar, probs[g].m, probs[g].n, probs[g].k, probs[g].k + probs[g].oversample, false);
+    // partial sums of the grouped Grams (shared by every CholeskyQR2 stage, which run in turn)
+    size_t o_gpart = 0;
+    {
+        std::vector<int64_t> mr(count), nr(count), pr(count);
+        for (int32_t g = 0; g < count; ++g) {
+            mr[g] = probs[g].m;
+            nr[g] = probs[g].n;
+            pr[g] = probs[g].k + probs[g].oversample;
+        }
+        const size_t bm = gram_part_bytes(mr, pr), bn = gram_part_bytes(nr, pr);
+        o_gpart = ar.take(bm > bn ? bm : bn);
+    }
+    const size_t o_tnpart = ar.take(tn_part_bytes(probs, count));
     if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
     char* base = static_cast<char*>(ctx->ws);
     for (int32_t g = 0; g < count; ++g) pk[g].data = base + o_pk[g];
@@ -1503,7 +1683,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     // fast kernels, the others to the general one)
     std::vector<rpmi::ProjArgs> grouped, grouped_fast;
     std::vector<int> single;
-    uint64_t sig = mix(0, (uint64_t)count);
+    uint64_t sig = mix(mix(0, (uint64_t)count), (uint64_t)ctx->num_cus);
     for (int32_t g = 0; g < count; ++g) {
         const rp_rsvd_problem& q = probs[g];
         const rp_desc dA{q.A, q.m, q.n, q.lda, q.n, 1, 0};
@@ -1583,6 +1763,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             ctx->tuned_scale[sig] = best;
+            if (!ctx->tuning_file.empty()) (void)tuning_save(ctx, ctx->tuning_file.c_str());
         }
         if ((st = plan_group(ctx, grouped, best, &gp)) != RP_OK) return st;
         if (gp.entries.size() > ctx->graph_table_entries) {
@@ -1630,10 +1811,11 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
             zs[g] = ws[g].Z;
             wsp[g] = ws[g].W;
         }
-        cq_yq = build_cholqr2_group(im, mrows, ys, qs, ws, false);
-        if (power_iters > 0) cq_zw = build_cholqr2_group(im, nrows, zs, wsp, ws, false);
-        cq_zw_m = build_cholqr2_group(im, nrows, zs, wsp, ws, true);
-        tn = build_tn_group(im, probs, ws);
+        char* gpart = base + o_gpart;
+        cq_yq = build_cholqr2_group(im, mrows, ys, qs, ws, false, gpart);
+        if (power_iters > 0) cq_zw = build_cholqr2_group(im, nrows, zs, wsp, ws, false, gpart);
+        cq_zw_m = build_cholqr2_group(im, nrows, zs, wsp, ws, true, gpart);
+        tn = build_tn_group(im, probs, ws, base + o_tnpart);
         fin = build_finish_group(im, probs, ws);
         if (im.bytes.size() > ctx->graph_aux_bytes) {
             if (ctx->graph_aux) RP_HIP(ctx, hipFree(ctx->graph_aux));

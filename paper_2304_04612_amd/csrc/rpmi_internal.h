@@ -262,7 +262,24 @@ int64_t gemm_group_tiles_n(int64_t N);
 template <class TA, class TB, class TC>
 hipError_t gemm_acc64_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s);
 
-constexpr int kCholGroupMaxP = 199;   // p (p + 1) / 2 doubles of L fit in 160 KiB of LDS
+struct GramJob {                      // G (p x p, FP64) = Y^T Y, Y (R x p, ld ldy, FP32 or FP64)
+    const void* y;
+    int64_t ldy, R, p;
+    int64_t kchunk;                   // rows per contraction chunk
+    double* G;
+    double* part;                     // ksplit > 1: ksplit partial sums of p x p (G = their sum, in order)
+    int ksplit, tiles;                // tiles: upper-triangle 64 x 64 tiles of G
+    int64_t start;
+};
+int gram_group_tiles(int64_t p);
+// One launch for the partial (or direct) products of every job, a second
+// one (only when some job has ksplit > 1) for the sums; G is written whole
+// (both triangles, exactly symmetric).
+template <class T>
+hipError_t gram_group(const GramJob* jobs, const int64_t* starts, int count, int64_t blocks, bool any_split,
+                      hipStream_t s);
+
+constexpr int kCholGroupMaxP = 199;   // p (p + 1) / 2 + 2 p doubles fit in 160 KiB of LDS
 struct CholJob {                      // G (p x p) = L L^T; L (lower, zero above) and X = L^-1
     const double* G;
     double* L;                        // may equal G
@@ -279,13 +296,16 @@ struct TnJob {                        // C (N x P) = A^T Q, A K x N, Q K x P, al
     int64_t ldq;
     float* C;
     int64_t ldc;
-    int64_t tiles_x, start;
+    int64_t tiles_x, tiles_y, start;
+    int64_t kchunk;                   // rows of A per contraction chunk
+    int ksplit;                       // > 1: chunk kz writes part + kz N P (ld P); C = their sum, in order
+    float* part;
 };
 int64_t tn_group_tiles_x(int64_t P);
 int64_t tn_group_tiles(int64_t N, int64_t P);
 // vec: every job has 16-byte aligned A, Q, C and lda, ldq, ldc multiples of 4
 hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
-                             hipStream_t s);
+                             bool any_split, hipStream_t s);
 
 struct SvdJob {                       // after the Jacobi iteration on W (n x n) with V
     const double* W;

@@ -217,3 +217,45 @@ def test_rsvd_batched_wide_and_breakdown():
     announce("rsvd_batched with a zero matrix (grouped stages)")
     rp().rsvd_batched([dev(b), dev(np.zeros((300, 260), np.float32))], [12, 12], [10, 10], 0, 19, "f16")
     assert rp().rp_get_device_status(clear=True) == rp().RP_ERR_NOT_SPD
+
+
+def test_tuning_cache_persists(tmp_path, monkeypatch):
+    """The autotuner's choice survives the context: saved, loaded into a
+    fresh context (same plan, so bit-identical results), picked up through
+    RPMI_TUNING_FILE and rewritten there after a new tuning; a file that does
+    not parse is an error."""
+    rng = np.random.default_rng(8)
+    shapes = [(300, 256), (200, 128), (520, 384), (96, 64)]
+    announce(f"tuning cache with rsvd_batched {shapes}")
+    mats = [dev(rng.standard_normal(s).astype(np.float32)) for s in shapes]
+    ks, ss = [8, 6, 10, 4], [8, 8, 8, 8]
+    c1 = rp().Context(0)
+    assert rp().rp_tuning_count(ctx=c1) == 0
+    out1 = rp().rsvd_batched(mats, ks, ss, 0, 5, "f16", ctx=c1)
+    n1 = rp().rp_tuning_count(ctx=c1)
+    assert n1 >= 1
+    path = tmp_path / "tune.txt"
+    rp().rp_tuning_save(str(path), ctx=c1)
+    assert len(path.read_text().split("\n")) - 1 == n1
+    c2 = rp().Context(0)
+    rp().rp_tuning_load(str(path), ctx=c2)
+    assert rp().rp_tuning_count(ctx=c2) == n1
+    out2 = rp().rsvd_batched(mats, ks, ss, 0, 5, "f16", ctx=c2)
+    assert rp().rp_tuning_count(ctx=c2) == n1          # nothing new to tune
+    for (u1, s1, v1), (u2, s2, v2) in zip(out1, out2):
+        assert np.array_equal(host(s1), host(s2))
+        assert np.array_equal(host(u1), host(u2))
+    monkeypatch.setenv("RPMI_TUNING_FILE", str(path))
+    c3 = rp().Context(0)
+    assert rp().rp_tuning_count(ctx=c3) == n1
+    rp().rsvd_batched(mats[:2], ks[:2], ss[:2], 0, 5, "f16", ctx=c3)   # a new signature
+    assert rp().rp_tuning_count(ctx=c3) == n1 + 1
+    assert len(path.read_text().split("\n")) - 1 == n1 + 1
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a tuning line\n")
+    with pytest.raises(rp().RpError):
+        rp().rp_tuning_load(str(bad), ctx=c2)
+    with pytest.raises(rp().RpError):
+        rp().rp_tuning_load(str(tmp_path / "missing.txt"), ctx=c2)
+    for c in (c1, c2, c3):
+        c.close()
