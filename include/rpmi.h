@@ -387,8 +387,9 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
  * linear index of the remaining modes.  Omega_i (prod_{l != i} dims[l] x J_i)
  * is generated from (seed, stream_id = i) in omega_type; the projections run
  * with `algo` (RP_ALGO_SPLIT_F16: all modes whose unfolding can be streamed in
- * place go out in one grouped launch; a mode whose columns are not contiguous
- * in runs of a multiple of 64 elements, the last mode among them, is first
+ * place go out in grouped launches; the last mode streams X in place through
+ * the transposed split kernel (see rp_hosvd_project); any other mode whose
+ * columns are not contiguous in runs of a multiple of 64 elements is first
  * copied mode-first into workspace).  Each QR is CholeskyQR2 (FP64 Gram,
  * Cholesky and triangular inverse), so Q_i is the orthonormal factor with a
  * positive-diagonal R.  The core is contracted one mode at a time: the first
@@ -407,6 +408,24 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
 rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X,
                    const int64_t* ranks, uint64_t seed, rp_omega_t omega_type,
                    rp_algo_t algo, float* core, float* const* factors, void* stream);
+
+/*
+ * The projection step of RP-HOSVD alone (Algorithm 2 line 2, every mode):
+ * W_i = X_(i) Omega_i into W[i] (device, dims[i] x J_i row-major, leading
+ * dimension ldw[i] >= J_i), with the same X, dims, ranks, Omega_i and
+ * arguments checks as rp_hosvd, and the same launches: with
+ * RP_ALGO_SPLIT_F16 the modes whose unfolding streams in place go out
+ * grouped, and the last mode, when dims[ndim-1] is a multiple of 4 and X is
+ * 16-byte aligned, runs as W = M^T Omega for M = X viewed as
+ * (prod_{l<N} dims[l]) x dims[N-1] row-major, on the transposed split kernel
+ * (every element of X split into hi and lo as in eq:shgemm-1/2, both
+ * against the FP16 Omega, one FP32 accumulator; X read in place); other
+ * layouts are copied mode-first first.  W, ldw: host arrays of ndim entries.
+ * Device condition: RP_ERR_RANGE (split path, X outside the FP16 range).
+ */
+rp_status rp_hosvd_project(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X,
+                           const int64_t* ranks, uint64_t seed, rp_omega_t omega_type,
+                           rp_algo_t algo, float* const* W, const int64_t* ldw, void* stream);
 
 /*
  * Split of an FP32 array into FP16 hi and lo (Sec. 4.1, eq:shgemm-1/2), as the
@@ -430,11 +449,16 @@ rp_status rp_get_device_status(rp_ctx ctx, void* stream, int clear, rp_status* o
 /*
  * Autotuner cache of the grouped projections (the batching of Sec. 5's
  * many-problem runs and of Algorithm 2's per-mode projections): the first
- * rsvd_batched call on a problem-shape signature times the grouped launch
- * at several contraction-split scales (the CU share each problem's split is
- * planned for) and keeps the fastest per context.  The cache persists:
+ * rsvd_batched, rp_project_grouped, rp_hosvd or rp_hosvd_project call on a
+ * problem set (shapes and layouts) times its grouped launch at several
+ * contraction-split scales (the CU share each problem's split is planned
+ * for), times two kernel forms for the 16-byte-path problems with r <= 128
+ * (register-staged 128-row tiles, LDS-staged 256-row tiles), and keeps the
+ * fastest per context; a stream under graph capture is not timed (scale 1,
+ * register-staged form).  RPMI_GROUP_FORM=0 or 1 in the environment at
+ * rp_create fixes the form.  The cache persists:
  *   - rp_tuning_save writes every entry to `path` as text, one line
- *     "<signature hex> <scale>" per entry (replacing the file);
+ *     "<signature hex> <scale> <form>" per entry (replacing the file);
  *   - rp_tuning_load adds the entries of such a file (later lines win);
  *     a line that does not parse stops the load with RP_ERR_INVALID_ARG
  *     (entries read before it are kept); a missing file is RP_ERR_INVALID_ARG;

@@ -86,6 +86,7 @@ def lib():
                  ctypes.c_size_t, vp],
         "rsvd_workspace_size": [vp, i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "rp_hosvd": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
+        "rp_hosvd_project": [vp, i32, vp, vp, vp, u64, i32, i32, vp, vp, vp],
         "rp_project_grouped": [vp, i32, vp, i32, vp],
         "rp_omega_generate_e4m3": [vp, u64, u32, i64, i64, vp, i64, vp, vp],
         "rsvd_batched": [vp, i32, vp, i32, u64, i32, vp],
@@ -331,6 +332,29 @@ def rp_hosvd(x, ranks, seed=0, omega_type="f16", algo="split_f16", ctx=None):
     _check(ctx.handle, lib().rp_hosvd(ctx.handle, nd, dims_c, _ptr(x), ranks_c, seed, OMEGA_TYPES[omega_type],
                                       ALGOS[algo], _ptr(core), fac_c, _stream()))
     return core, factors
+
+
+def rp_hosvd_project(x, ranks, seed=0, omega_type="f16", algo="split_f16", out=None, ctx=None):
+    """Algorithm 2 line 2 alone: [W_i = X_(i) Omega_i] (float32 dims[i] x
+    ranks[i]) for the C-contiguous float32 CUDA tensor ``x``."""
+    import torch
+    ctx = ctx or default_context()
+    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a C-contiguous float32 CUDA tensor")
+    nd = x.dim()
+    ranks = [int(r) for r in ranks]
+    if len(ranks) != nd:
+        raise ValueError("one rank per mode")
+    dev = f"cuda:{ctx.device}"
+    ws = out if out is not None else [torch.empty((x.shape[i], ranks[i]), dtype=torch.float32, device=dev)
+                                      for i in range(nd)]
+    dims_c = (ctypes.c_int64 * nd)(*x.shape)
+    ranks_c = (ctypes.c_int64 * nd)(*ranks)
+    w_c = (ctypes.c_void_p * nd)(*[_ptr(w) for w in ws])
+    ld_c = (ctypes.c_int64 * nd)(*[w.stride(0) for w in ws])
+    _check(ctx.handle, lib().rp_hosvd_project(ctx.handle, nd, dims_c, _ptr(x), ranks_c, seed, OMEGA_TYPES[omega_type],
+                                              ALGOS[algo], w_c, ld_c, _stream()))
+    return ws
 
 
 def rp_omega_generate_e4m3(n, r, seed=0, stream_id=0, ctx=None):

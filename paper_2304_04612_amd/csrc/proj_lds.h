@@ -108,7 +108,9 @@ __device__ __forceinline__ void split8_fold(const floatx4& a0, const floatx4& a1
     y = __builtin_bit_cast(half8, u32x4{y0, y1, y2, y3});
 }
 
-template <class C, bool FOLD, bool TCEC = false>
+// PARTIAL (grouped exact form): with a contraction split only the partial
+// sums are written; split_lds_group_reduce_kernel adds them.
+template <class C, bool FOLD, bool TCEC = false, bool PARTIAL = false>
 __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t bm, const int64_t bn, const int kz,
                                                const int64_t tiles_n) {
     static_assert(!(FOLD && TCEC), "the TCEC products take the exact split");
@@ -349,11 +351,11 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
         for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
             for (int j = 0; j < TN; ++j) mine[(tm * TN + j) * C::THREADS + tid] = acc[tm][j];
-        // single forms (folded, TCEC): a second kernel (split_lds_reduce_kernel)
-        // adds the partials, so no workgroup waits on a device-scope release
-        // (an L2 write-back on this chip); grouped form: the last workgroup of
-        // the tile to arrive adds all ksplit partials in order z = 0, 1, ...
-        if constexpr (FOLD || TCEC) return;
+        // a second kernel (split_lds_reduce_kernel, or the grouped one) adds
+        // the partials, so no workgroup waits on a device-scope release (an L2
+        // write-back on this chip); otherwise the last workgroup of the tile
+        // to arrive adds all ksplit partials in order z = 0, 1, ...
+        if constexpr (FOLD || TCEC || PARTIAL) return;
         __threadfence();
         __shared__ unsigned int arrival;
         __syncthreads();
@@ -390,6 +392,8 @@ __device__ __forceinline__ void split_lds_body(const ProjArgs& p, const int64_t 
 // Several independent projections in one launch (exact form): dense block b
 // (see xcd_dense_block) belongs to the problem g with table[g].start <= b <
 // table[g + 1].start; inside it, blocks enumerate (kz, bm, bn) with bn fastest.
+// A problem with a contraction split leaves partial sums for
+// split_lds_group_reduce_kernel.
 template <class C>
 __global__ __launch_bounds__(C::THREADS, 1) void project_split_lds_grouped_kernel(const GroupEntry* __restrict__ table,
                                                                                  int count) {
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(C::THREADS, 1) void project_split_lds_grouped_kerne
     const int64_t per_k = tm * tn;
     const int kz = (int)(local / per_k);
     const int64_t rest = local - kz * per_k;
-    split_lds_body<C, false>(e.p, rest / tn, rest % tn, kz, tn);
+    split_lds_body<C, false, false, true>(e.p, rest / tn, rest % tn, kz, tn);
 }
 
 // One projection (folded form), its arguments by value (kernel argument
@@ -420,6 +424,11 @@ __global__ __launch_bounds__(C::THREADS, 1) void project_split_lds_single_kernel
     const int64_t rest = b - kz * per_k;
     split_lds_body<C, true>(p, rest / tn, rest % tn, kz, tn);
 }
+
+// r <= 128 in the LDS-staged form: 128-column tiles, 8 waves of 32 rows (BM =
+// 256); an alternative to the register-staged narrow kernel that the
+// grouped launches' autotuner may pick
+using NarrowLdsCfg = LdsCfg<8, 2, 8, 3>;
 
 // TCEC products (eq:tcec-5, both operands split): 128-column tiles, so that
 // the three stages hold A and both Omega arrays (3 x 48 KiB).
@@ -434,17 +443,16 @@ __global__ __launch_bounds__(C::THREADS, 1) void project_tcec_lds_kernel(ProjArg
     split_lds_body<C, false, true>(p, rest / tn, rest % tn, kz, tn);
 }
 
-// Second pass of a folded or TCEC projection with a contraction split: Y = 2^-11 y_scale
+// Second pass of a projection with a contraction split: Y = 2^-11 y_scale
 // sum_z partial_z, summed in the fixed order z = 0, 1, ... (the result does not
 // depend on the order in which the first pass's workgroups ran).  One block
 // per (tile, fragment); thread t of the block holds what thread t of the
 // first pass's workgroup held for that fragment.
 template <class C>
-__global__ __launch_bounds__(C::THREADS) void split_lds_reduce_kernel(ProjArgs p) {
+__device__ __forceinline__ void split_lds_reduce_body(const ProjArgs& p, int64_t tn, int64_t rb) {
     constexpr int TM = C::TM, TN = C::TN, NF = TM * TN, TILE_F4 = NF * C::THREADS;
-    const int64_t tn = (p.r + C::BN - 1) / C::BN;
-    const int64_t tile = blockIdx.x / NF;
-    const int f = (int)(blockIdx.x % NF), tm = f / TN, j = f % TN;
+    const int64_t tile = rb / NF;
+    const int f = (int)(rb % NF), tm = f / TN, j = f % TN;
     const int64_t bm = tile / tn, bn = tile % tn;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
     const floatx4* src = reinterpret_cast<const floatx4*>(p.partial) + tile * p.ksplit * TILE_F4 + f * C::THREADS + tid;
@@ -457,6 +465,29 @@ __global__ __launch_bounds__(C::THREADS) void split_lds_reduce_kernel(ProjArgs p
         const int64_t row = bm * C::BM + (wave * TM + tm) * 16 + 4 * g + e;
         if (row < p.m && col < p.r) p.Y[row * p.ldy + col] = sum[e] * yscale;
     }
+}
+
+// single folded or TCEC projection
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void split_lds_reduce_kernel(ProjArgs p) {
+    split_lds_reduce_body<C>(p, (p.r + C::BN - 1) / C::BN, blockIdx.x);
+}
+
+// grouped launch: block b belongs to the problem g with table[g].rstart <= b
+// < table[g + 1].rstart (problems without a split own no blocks)
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void split_lds_group_reduce_kernel(const GroupEntry* __restrict__ table,
+                                                                            int count) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+#pragma unroll 1
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].rstart <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupEntry& e = table[lo];
+    split_lds_reduce_body<C>(e.p, e.tiles_n, b - e.rstart);
 }
 
 }  // namespace

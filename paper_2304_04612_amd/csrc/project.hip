@@ -303,6 +303,7 @@ int64_t split_f16_col_block(int64_t r) { return r <= 128 ? 128 : 256; }
 int64_t f32_col_block() { return F32Tile::BN; }
 int64_t proj_k_block() { return 64; }   // multiple of every tile's step (SplitTile 64, DmaTile 32, F32Tile 32)
 static_assert(64 % SplitTile::BK == 0 && 64 % DmaTile::BK == 0 && 64 % F32Tile::BK == 0, "k block");
+static_assert(NarrowLdsCfg::BN == 128 && NarrowLdsCfg::BN == DmaTile128::BN, "both narrow forms read one packing");
 static_assert(SplitTile::BN == DmaTile::BN && SplitTile128::BN == DmaTile128::BN && DmaTile128::BN == 128 &&
               DmaTile::BN == 256, "both split paths read the same packed Omega");
 
@@ -328,6 +329,11 @@ SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus) {
     return r <= kNarrowMax ? plan_for<NarrowCfg>(m, n, r, num_cus) : plan_for<WideCfg>(m, n, r, num_cus);
 }
 
+SplitPlan plan_split_f16_narrow_lds(int64_t m, int64_t n, int64_t r, int num_cus) {
+    return plan_for<NarrowLdsCfg>(m, n, r, num_cus);
+}
+int64_t split_group_tile_m_narrow_lds() { return NarrowLdsCfg::BM; }
+
 int64_t split_group_tile_m(int64_t r) { return r <= 128 ? DmaTile128::BM : DmaTile::BM; }
 int64_t split_group_tile_n(int64_t r) { return r <= 128 ? DmaTile128::BN : DmaTile::BN; }
 
@@ -348,9 +354,9 @@ hipError_t launch_project_tcec(const ProjArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                            hipStream_t s, const GroupEntry* one) {
+                                            hipStream_t s, const GroupEntry* one, int64_t rblocks) {
     return narrow ? launch_split_group_narrow(table, count, blocks, one, s)
-                  : launch_split_group_wide(table, count, blocks, one, s);
+                  : launch_split_group_wide(table, count, blocks, one, s, rblocks);
 }
 
 // A single projection on the 16-byte path goes to the fast kernel of its
@@ -371,6 +377,7 @@ hipError_t launch_split_with(const ProjArgs& a, hipStream_t s) {
         e.tiles_m = (a.m + TD::BM - 1) / TD::BM;
         e.tiles_n = (a.r + TD::BN - 1) / TD::BN;
         e.start = 0;
+        e.rstart = 0;
         hipError_t err = launch_project_split_f16_grouped(nullptr, 0, e.tiles_m * e.tiles_n * (a.ksplit > 1 ? a.ksplit : 1),
                                                           !wide, s, &e);
         if (err != hipSuccess || !wide) return err;

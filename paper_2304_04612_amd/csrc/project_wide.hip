@@ -6,7 +6,7 @@
 namespace rpmi {
 
 hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
-                                   hipStream_t s) {
+                                   hipStream_t s, int64_t rblocks) {
     if (blocks <= 0 || (count <= 0 && !one)) return hipSuccess;
     using C = WideCfg;
     if (one) {
@@ -18,9 +18,13 @@ hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t b
                                0, s, one->p);
         }
     }
-    else
+    else {
         hipLaunchKernelGGL((project_split_lds_grouped_kernel<C>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                            table, count);
+        if (rblocks > 0)
+            hipLaunchKernelGGL((split_lds_group_reduce_kernel<C>), dim3((unsigned)rblocks), dim3(C::THREADS), 0, s,
+                               table, count);
+    }
     return hipGetLastError();
 }
 

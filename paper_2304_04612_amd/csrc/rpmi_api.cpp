@@ -53,8 +53,16 @@ struct rp_ctx_s {
     size_t graph_jtab_entries = 0;
     char* graph_aux = nullptr;                // job tables of the grouped stages read by the graph
     size_t graph_aux_bytes = 0;
-    std::unordered_map<uint64_t, double> tuned_scale;
+    // autotuner cache of the grouped projections: per problem-set signature
+    // the contraction-split scale and the narrow kernel form (0: register-
+    // staged, 1: LDS-staged)
+    struct TuneEntry {
+        double scale;
+        int form;
+    };
+    std::unordered_map<uint64_t, TuneEntry> tuned_scale;
     std::string tuning_file;              // RPMI_TUNING_FILE at creation ("" if unset)
+    int force_form = -1;                  // RPMI_GROUP_FORM at creation (0 or 1), else -1
     // generated Omega kept in device memory, keyed by what defines its bits
     // (seed, stream_id, n, r, type) and by the fragment format (algorithm);
     // least recently used entries are freed beyond kOmegaCacheBytes
@@ -172,13 +180,15 @@ rp_status tuning_load(rp_ctx ctx, const char* path) {
         ++lineno;
         unsigned long long key = 0;
         double scale = 0.0;
+        int form = 0;
         char extra = 0;
         if (line[0] == '\n' || line[0] == '\0') continue;
-        if (sscanf(line, "%llx %lf %c", &key, &scale, &extra) != 2 || !(scale > 0.0) || scale > 64.0) {
+        if (sscanf(line, "%llx %lf %d %c", &key, &scale, &form, &extra) != 3 || !(scale > 0.0) || scale > 64.0 ||
+            form < 0 || form > 1) {
             st = fail(ctx, RP_ERR_INVALID_ARG, "tuning file %s line %d does not parse", path, lineno);
             break;
         }
-        ctx->tuned_scale[(uint64_t)key] = scale;
+        ctx->tuned_scale[(uint64_t)key] = rp_ctx_s::TuneEntry{scale, form};
     }
     fclose(f);
     return st;
@@ -187,7 +197,8 @@ rp_status tuning_load(rp_ctx ctx, const char* path) {
 rp_status tuning_save(rp_ctx ctx, const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return fail(ctx, RP_ERR_INVALID_ARG, "cannot write tuning file %s", path);
-    for (const auto& e : ctx->tuned_scale) fprintf(f, "%016llx %.17g\n", (unsigned long long)e.first, e.second);
+    for (const auto& e : ctx->tuned_scale)
+        fprintf(f, "%016llx %.17g %d\n", (unsigned long long)e.first, e.second.scale, e.second.form);
     const bool ok = fclose(f) == 0;
     return ok ? RP_OK : fail(ctx, RP_ERR_INVALID_ARG, "writing tuning file %s failed", path);
 }
@@ -244,6 +255,10 @@ rp_status rp_create(rp_ctx* out, int device) {
         if ((e = rpmi::noalloc_scratch_address(&p)) != hipSuccess || !p)
             return cleanup(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
         ctx->noalloc_scratch = static_cast<unsigned char*>(p);
+    }
+    if (const char* ff = getenv("RPMI_GROUP_FORM")) {
+        if (ff[0] == '0' && ff[1] == '\0') ctx->force_form = 0;
+        if (ff[0] == '1' && ff[1] == '\0') ctx->force_form = 1;
     }
     if (const char* tf = getenv("RPMI_TUNING_FILE")) {
         if (tf[0]) {
@@ -650,12 +665,15 @@ struct GroupPlan {
     struct Seg {
         int first = 0, count = 0;
         int64_t blocks = 0;
+        int64_t rblocks = 0;   // reduction-pass blocks (LDS-staged launches)
     };
     std::vector<rpmi::GroupEntry> entries;
     Seg seg[4];   // fast narrow, fast wide, general narrow, general wide
+    bool narrow_lds = false;   // fast narrow problems on the LDS-staged kernel
 };
 
-rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, double cu_scale, GroupPlan* out) {
+rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, double cu_scale, GroupPlan* out,
+                     bool narrow_lds = false) {
     std::vector<int> fast, general;
     double total = 0;
     for (size_t g = 0; g < probs.size(); ++g) {
@@ -674,7 +692,8 @@ rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, doubl
     for (int g : fast) {
         const auto& a = probs[g];
         const int share = (int)(cus * cu_scale * ((double)a.m * a.n / total) + 0.5);
-        plans[g] = rpmi::plan_split_f16(a.m, a.n, a.r, share > 0 ? share : 1);
+        plans[g] = narrow_lds && a.r <= 128 ? rpmi::plan_split_f16_narrow_lds(a.m, a.n, a.r, share > 0 ? share : 1)
+                                             : rpmi::plan_split_f16(a.m, a.n, a.r, share > 0 ? share : 1);
         counter_bytes += (plans[g].counter_bytes + 255) & ~size_t(255);
         partial_bytes += (plans[g].partial_bytes + 255) & ~size_t(255);
     }
@@ -685,11 +704,13 @@ rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, doubl
     char* cbase = reinterpret_cast<char*>(ctx->split_counters);
     char* pbase = static_cast<char*>(ctx->split_ws);
     out->entries.clear();
+    out->narrow_lds = narrow_lds;
     for (int sg = 0; sg < 4; ++sg) {
         const bool gen = sg >= 2, narrow = (sg & 1) == 0;
         GroupPlan::Seg& seg = out->seg[sg];
         seg.first = (int)out->entries.size();
-        int64_t start = 0;
+        int64_t start = 0, rstart = 0;
+        const bool lds = sg == 1 || (sg == 0 && narrow_lds);
         for (int g : gen ? general : fast) {
             if ((probs[g].r <= 128) != narrow) continue;
             rpmi::GroupEntry e;
@@ -708,17 +729,20 @@ rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, doubl
                 e.p.partial = e.p.ksplit > 1 ? reinterpret_cast<float*>(pbase) : nullptr;
                 cbase += (plans[g].counter_bytes + 255) & ~size_t(255);
                 pbase += (plans[g].partial_bytes + 255) & ~size_t(255);
-                bm = rpmi::split_group_tile_m(e.p.r);
+                bm = narrow && narrow_lds ? rpmi::split_group_tile_m_narrow_lds() : rpmi::split_group_tile_m(e.p.r);
                 bn = rpmi::split_group_tile_n(e.p.r);
             }
             e.tiles_m = (e.p.m + bm - 1) / bm;
             e.tiles_n = (e.p.r + bn - 1) / bn;
             e.start = start;
             start += e.tiles_m * e.tiles_n * e.p.ksplit;
+            e.rstart = rstart;
+            if (lds && e.p.ksplit > 1) rstart += rpmi::split_group_reduce_blocks(e.tiles_m * e.tiles_n, sg == 0);
             out->entries.push_back(e);
         }
         seg.count = (int)out->entries.size() - seg.first;
         seg.blocks = start;
+        seg.rblocks = rstart;
     }
     return RP_OK;
 }
@@ -728,8 +752,11 @@ rp_status launch_group_kernels(rp_ctx ctx, const GroupPlan& gp, const rpmi::Grou
     for (int sg = 0; sg < 4; ++sg) {
         const GroupPlan::Seg& seg = gp.seg[sg];
         if (seg.count == 0) continue;
-        if (sg < 2)
-            RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table + seg.first, seg.count, seg.blocks, sg == 0, s));
+        if (sg == 0 && gp.narrow_lds)
+            RP_HIP(ctx, rpmi::launch_split_group_narrow_lds(table + seg.first, seg.count, seg.blocks, seg.rblocks, s));
+        else if (sg < 2)
+            RP_HIP(ctx, rpmi::launch_project_split_f16_grouped(table + seg.first, seg.count, seg.blocks, sg == 0, s,
+                                                               nullptr, seg.rblocks));
         else
             RP_HIP(ctx, rpmi::launch_project_split_f16_general_grouped(table + seg.first, seg.count, seg.blocks,
                                                                        sg == 2, s));
@@ -745,6 +772,77 @@ rp_status launch_group(rp_ctx ctx, const GroupPlan& gp, rpmi::GroupEntry* table,
     return launch_group_kernels(ctx, gp, table, s);
 }
 
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+// Autotuner of the grouped launches: time the launch of `probs` on `s` at
+// every candidate (contraction-split scale x narrow kernel form; the form
+// only where a narrow problem is on the 16-byte path) and keep the fastest
+// under `sig` (each trial writes the problems' outputs).
+rp_status tune_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, uint64_t sig, hipStream_t s,
+                     rp_ctx_s::TuneEntry* out) {
+    bool any_narrow = false;
+    for (const auto& a : probs) any_narrow = any_narrow || (a.r <= 128 && rpmi::split_fast_ok(a));
+    rp_status st;
+    GroupPlan gp;
+    hipEvent_t e0, e1;
+    RP_HIP(ctx, hipEventCreate(&e0));
+    RP_HIP(ctx, hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    const int f0 = ctx->force_form >= 0 ? ctx->force_form : 0;
+    const int f1 = ctx->force_form >= 0 ? ctx->force_form : (any_narrow ? 1 : 0);
+    *out = rp_ctx_s::TuneEntry{1.0, f0};
+    for (int form = f0; form <= f1; ++form)
+        for (double scale : {0.5, 1.0, 2.0, 4.0}) {
+            if ((st = plan_group(ctx, probs, scale, &gp, form == 1)) != RP_OK) return st;
+            if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
+            if ((st = launch_group(ctx, gp, ctx->table, s)) != RP_OK) return st;   // warm-up
+            RP_HIP(ctx, hipEventRecord(e0, s));
+            for (int rep = 0; rep < 3; ++rep)
+                if ((st = launch_group(ctx, gp, ctx->table, s)) != RP_OK) return st;
+            RP_HIP(ctx, hipEventRecord(e1, s));
+            RP_HIP(ctx, hipEventSynchronize(e1));
+            float ms = 0;
+            RP_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                *out = rp_ctx_s::TuneEntry{scale, form};
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned_scale[sig] = *out;
+    if (!ctx->tuning_file.empty()) (void)tuning_save(ctx, ctx->tuning_file.c_str());
+    return RP_OK;
+}
+
+// The plan of a grouped launch with the autotuner's choice for this problem
+// set (shapes and layouts), tuned now on a miss.  A stream under graph
+// capture takes scale 1 and the register-staged form untimed.
+rp_status tuned_group_plan(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, hipStream_t s, GroupPlan* gp) {
+    uint64_t sig = mix(mix(0x67726f7570ull, (uint64_t)probs.size()), (uint64_t)ctx->num_cus);
+    bool any_fast = false;
+    for (const auto& a : probs) {
+        sig = mix(mix(mix(mix(sig, (uint64_t)a.m), (uint64_t)a.n), (uint64_t)a.r), (uint64_t)a.s_row);
+        sig = mix(mix(mix(sig, (uint64_t)a.k_inner), (uint64_t)a.s_k_outer), (uint64_t)rpmi::split_fast_ok(a));
+        any_fast = any_fast || rpmi::split_fast_ok(a);
+    }
+    rp_ctx_s::TuneEntry best{1.0, 0};
+    auto it = ctx->tuned_scale.find(sig);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    RP_HIP(ctx, hipStreamIsCapturing(s, &cap));
+    if (it != ctx->tuned_scale.end()) {
+        best = it->second;
+    } else if (any_fast && cap == hipStreamCaptureStatusNone) {
+        rp_status st = tune_group(ctx, probs, sig, s, &best);
+        if (st != RP_OK) return st;
+    }
+    if (ctx->force_form >= 0) best.form = ctx->force_form;
+    return plan_group(ctx, probs, best.scale, gp, best.form == 1);
+}
+
 // Several split-FP16 projections in grouped launches.  Returns
 // RP_ERR_UNSUPPORTED (nothing launched) when a problem is empty; the caller
 // then launches them one by one.
@@ -758,7 +856,7 @@ rp_status launch_projection_grouped(rp_ctx ctx, int count, const rp_desc* const*
         probs[g] = proj_args(ctx, A[g], r[g], pk[g].data, pk[g].nt_count, Y[g], ldy[g], 0);
     }
     GroupPlan gp;
-    rp_status st = plan_group(ctx, probs, 1.0, &gp);
+    rp_status st = tuned_group_plan(ctx, probs, s, &gp);
     if (st != RP_OK) return st;
     if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
     return launch_group(ctx, gp, ctx->table, s);
@@ -1459,10 +1557,6 @@ rp_status run_finish_group(rp_ctx ctx, const FinishGroup& F, char* aux, hipStrea
     return RP_OK;
 }
 
-uint64_t mix(uint64_t h, uint64_t v) {
-    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
-    return h;
-}
 
 }  // namespace
 
@@ -1619,7 +1713,7 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
     }
     if (grouped.empty()) return RP_OK;
     GroupPlan gp;
-    if ((st = plan_group(ctx, grouped, 1.0, &gp)) != RP_OK) return st;
+    if ((st = tuned_group_plan(ctx, grouped, s, &gp)) != RP_OK) return st;
     if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
     return launch_group(ctx, gp, ctx->table, s);
 }
@@ -1732,40 +1826,21 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     hipStream_t cs = ctx->cap_stream;
 
     // autotuner: the contraction split of every grouped problem on the
-    // 16-byte path follows its share of the compute units times a scale; the
-    // scale is chosen once per problem-shape signature by timing the fast
-    // grouped launches
+    // 16-byte path follows its share of the compute units times a scale, and
+    // the narrow ones take one of two kernel forms; both are chosen once per
+    // problem-shape signature by timing the fast grouped launches
     GroupPlan gp;
     if (!grouped.empty()) {
         auto it = ctx->tuned_scale.find(sig);
-        double best = 1.0;
-        if (it != ctx->tuned_scale.end() || grouped_fast.empty()) {
-            if (it != ctx->tuned_scale.end()) best = it->second;
-        } else {
+        rp_ctx_s::TuneEntry best{1.0, 0};
+        if (it != ctx->tuned_scale.end()) {
+            best = it->second;
+        } else if (!grouped_fast.empty()) {
             if ((st = gen_omega(cs)) != RP_OK) return st;
-            hipEvent_t e0, e1;
-            RP_HIP(ctx, hipEventCreate(&e0));
-            RP_HIP(ctx, hipEventCreate(&e1));
-            float best_ms = 1e30f;
-            for (double scale : {0.5, 1.0, 2.0, 4.0}) {
-                if ((st = plan_group(ctx, grouped_fast, scale, &gp)) != RP_OK) return st;
-                if ((st = ensure_table(ctx, gp.entries.size())) != RP_OK) return st;
-                if ((st = launch_group(ctx, gp, ctx->table, cs)) != RP_OK) return st;   // warm-up
-                RP_HIP(ctx, hipEventRecord(e0, cs));
-                for (int rep = 0; rep < 3; ++rep)
-                    if ((st = launch_group(ctx, gp, ctx->table, cs)) != RP_OK) return st;
-                RP_HIP(ctx, hipEventRecord(e1, cs));
-                RP_HIP(ctx, hipEventSynchronize(e1));
-                float ms = 0;
-                RP_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) { best_ms = ms; best = scale; }
-            }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            ctx->tuned_scale[sig] = best;
-            if (!ctx->tuning_file.empty()) (void)tuning_save(ctx, ctx->tuning_file.c_str());
+            if ((st = tune_group(ctx, grouped_fast, sig, cs, &best)) != RP_OK) return st;
         }
-        if ((st = plan_group(ctx, grouped, best, &gp)) != RP_OK) return st;
+        if (ctx->force_form >= 0) best.form = ctx->force_form;
+        if ((st = plan_group(ctx, grouped, best.scale, &gp, best.form == 1)) != RP_OK) return st;
         if (gp.entries.size() > ctx->graph_table_entries) {
             if (ctx->graph_table) RP_HIP(ctx, hipFree(ctx->graph_table));
             ctx->graph_table = nullptr;
@@ -1904,9 +1979,35 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     return RP_OK;
 }
 
-rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X, const int64_t* ranks,
-                   uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* core, float* const* factors,
-                   void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Algorithm 2 line 2 for every mode (W_i = X_(i) Omega_i), shared by rp_hosvd
+// and rp_hosvd_project: the mode layouts, their workspace and the launches.
+//  * A mode whose unfolding streams in place (rows i_i, column runs of a
+//    multiple of 64 contiguous elements) is a plain projection; with the
+//    split algorithm all of them go out in grouped launches.
+//  * The last mode's unfolding is the transpose of X viewed as
+//    (total / I_N) x I_N row-major: W_N = X^T Omega_N on the transposed split
+//    kernel (X streamed in place, contraction split over its rows), when
+//    I_N is a multiple of 4 and X 16-byte aligned.
+//  * Any other mode is copied mode-first into workspace and projected.
+struct HosvdModes {
+    int N = 0;
+    int64_t total = 1;
+    int64_t after[rpmi::kMaxGroup], before[rpmi::kMaxGroup];
+    rp_desc desc[rpmi::kMaxGroup];
+    bool permuted[rpmi::kMaxGroup], tn_mode[rpmi::kMaxGroup];
+    int tn_split_k[rpmi::kMaxGroup];
+    int64_t tn_chunk[rpmi::kMaxGroup];
+    rpmi::PackedOmega pk[rpmi::kMaxGroup];
+    size_t o_pk[rpmi::kMaxGroup], o_tnp[rpmi::kMaxGroup];
+    size_t o_raw = 0, o_perm = 0;
+};
+
+rp_status hosvd_check(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X, const int64_t* ranks,
+                      rp_omega_t omega_type, rp_algo_t algo, float* const* outs, const char* what) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     rp_status st;
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
@@ -1914,42 +2015,173 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
         return fail(ctx, RP_ERR_INVALID_ARG, "the randomized algorithms project with RP_ALGO_F32 or RP_ALGO_SPLIT_F16");
     if (ndim < 2 || ndim > rpmi::kMaxGroup)
         return fail(ctx, RP_ERR_INVALID_ARG, "ndim %d outside [2, %d]", (int)ndim, rpmi::kMaxGroup);
-    if (!dims || !ranks || !X || !core || !factors) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
-    const int N = ndim;
+    if (!dims || !ranks || !X || !outs) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
     int64_t total = 1;
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < ndim; ++i) {
         if (dims[i] <= 0) return fail(ctx, RP_ERR_INVALID_ARG, "dims[%d] = %lld", i, (long long)dims[i]);
         total *= dims[i];
     }
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < ndim; ++i) {
         const int64_t cols = total / dims[i];
         if (ranks[i] <= 0 || ranks[i] > dims[i] || ranks[i] > cols || ranks[i] > 1024)
             return fail(ctx, RP_ERR_INVALID_ARG, "ranks[%d] = %lld must be in [1, min(dims[%d], %lld, 1024)]", i,
                         (long long)ranks[i], i, (long long)cols);
-        if (!factors[i]) return fail(ctx, RP_ERR_INVALID_ARG, "factors[%d] is NULL", i);
+        if (!outs[i]) return fail(ctx, RP_ERR_INVALID_ARG, "%s[%d] is NULL", what, i);
     }
     if (reinterpret_cast<uintptr_t>(X) & 3) return fail(ctx, RP_ERR_INVALID_ARG, "X is not 4-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    RP_HIP(ctx, hipSetDevice(ctx->device));
+    return RP_OK;
+}
 
+// Lay out the modes and take their workspace (packed Omega, raw Omega, the
+// mode-first copy, the transposed kernel's partial sums) from `ar`.
+void hosvd_plan_modes(rp_ctx ctx, int N, const int64_t* dims, const float* X, const int64_t* ranks,
+                      rp_omega_t omega_type, rp_algo_t algo, Arena& ar, HosvdModes& hm) {
+    hm.N = N;
+    hm.total = 1;
+    for (int i = 0; i < N; ++i) hm.total *= dims[i];
+    const int64_t total = hm.total;
     // mode-i unfolding of the C-order tensor: rows i_i, columns the C-order
     // index of the other modes = (leading index) * after + (trailing index);
     // element offset = i_i * after + lead * (dims[i] * after) + trail
-    int64_t after[rpmi::kMaxGroup], before[rpmi::kMaxGroup];
-    for (int i = N - 1, a = 1; i >= 0; --i) { after[i] = a; a *= dims[i]; }
-    for (int i = 0; i < N; ++i) before[i] = total / (dims[i] * after[i]);
-    rp_desc desc[rpmi::kMaxGroup];
-    bool permuted[rpmi::kMaxGroup];
-    int64_t maxr = 0, maxd = 0, perm_elems = 0;
+    for (int i = N - 1, a = 1; i >= 0; --i) { hm.after[i] = a; a *= dims[i]; }
+    for (int i = 0; i < N; ++i) hm.before[i] = total / (dims[i] * hm.after[i]);
+    int64_t perm_elems = 0;
+    const int cus = ctx->num_cus > 0 ? ctx->num_cus : 256;
+    for (int i = 0; i < N; ++i) {
+        const int64_t cols = total / dims[i], after = hm.after[i], before = hm.before[i];
+        hm.desc[i] = rp_desc{X, dims[i], cols, after, after == 1 && before > 1 ? 1 : after, 1, dims[i] * after};
+        if (before == 1) hm.desc[i].k_inner = cols;             // mode 1: plain row-major
+        rp_status dummy;
+        hm.permuted[i] = !(before == 1 || (after % rpmi::proj_k_block() == 0 && after > 1));
+        if (!hm.permuted[i] && !proj_layout_ok(ctx, &hm.desc[i], &dummy)) hm.permuted[i] = true;
+        hm.tn_mode[i] = hm.permuted[i] && algo == RP_ALGO_SPLIT_F16 && after == 1 && before > 1 &&
+                        dims[i] % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+        if (hm.permuted[i] && !hm.tn_mode[i]) perm_elems = total;
+        hm.tn_split_k[i] = 1;
+        hm.tn_chunk[i] = 0;
+        hm.o_tnp[i] = 0;
+        if (hm.tn_mode[i]) {
+            hm.tn_split_k[i] = rpmi::plan_tn_tcec_split(before, dims[i], ranks[i], cus, &hm.tn_chunk[i]);
+            if (hm.tn_split_k[i] > 1)
+                hm.o_tnp[i] = ar.take((size_t)hm.tn_split_k[i] * dims[i] * ranks[i] * sizeof(float));
+        }
+    }
+    size_t rawb = 0;
     for (int i = 0; i < N; ++i) {
         const int64_t cols = total / dims[i];
-        desc[i] = rp_desc{X, dims[i], cols, after[i], after[i] == 1 && before[i] > 1 ? 1 : after[i], 1,
-                          dims[i] * after[i]};
-        if (before[i] == 1) desc[i].k_inner = cols;             // mode 1: plain row-major
-        rp_status dummy;
-        permuted[i] = !(before[i] == 1 || (after[i] % rpmi::proj_k_block() == 0 && after[i] > 1));
-        if (!permuted[i] && !proj_layout_ok(ctx, &desc[i], &dummy)) permuted[i] = true;
-        if (permuted[i]) perm_elems = total;
+        hm.pk[i] = packed_geometry(cols, ranks[i], algo, nullptr);
+        hm.o_pk[i] = ar.take(packed_bytes(hm.pk[i], algo));
+        const size_t rb = raw_bytes(omega_type, algo, cols, ranks[i]);
+        rawb = rb > rawb ? rb : rawb;
+    }
+    hm.o_raw = ar.take(rawb);
+    hm.o_perm = ar.take((size_t)perm_elems * 4);
+}
+
+// Launch every mode's projection into W[i] (dims[i] x ranks[i], ld ldw[i]).
+rp_status hosvd_run_projections(rp_ctx ctx, HosvdModes& hm, const int64_t* dims, const float* X,
+                                const int64_t* ranks, uint64_t seed, rp_omega_t omega_type, rp_algo_t algo,
+                                float* const* W, const int64_t* ldw, hipStream_t s) {
+    const int N = hm.N;
+    char* base = static_cast<char*>(ctx->ws);
+    float* perm = reinterpret_cast<float*>(base + hm.o_perm);
+    rp_status st;
+    for (int i = 0; i < N; ++i) {
+        const int64_t cols = hm.total / dims[i];
+        st = cached_packed_omega(ctx, seed, (uint32_t)i, omega_type, cols, ranks[i], algo, base + hm.o_raw, s,
+                                 &hm.pk[i]);
+        if (st == RP_ERR_UNSUPPORTED) {
+            hm.pk[i].data = base + hm.o_pk[i];
+            st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, hm.pk[i],
+                             base + hm.o_raw, s);
+        }
+        if (st != RP_OK) return st;
+    }
+    bool grouped_done = false;
+    if (algo == RP_ALGO_SPLIT_F16) {
+        const rp_desc* gA[rpmi::kMaxGroup];
+        int64_t gr[rpmi::kMaxGroup], gld[rpmi::kMaxGroup];
+        rpmi::PackedOmega gpk[rpmi::kMaxGroup];
+        float* gY[rpmi::kMaxGroup];
+        int cnt = 0;
+        for (int i = 0; i < N; ++i) {
+            if (hm.permuted[i]) continue;
+            gA[cnt] = &hm.desc[i]; gr[cnt] = ranks[i]; gld[cnt] = ldw[i]; gpk[cnt] = hm.pk[i]; gY[cnt] = W[i];
+            ++cnt;
+        }
+        if (cnt > 1) {
+            st = launch_projection_grouped(ctx, cnt, gA, gr, gpk, gY, gld, s);
+            if (st == RP_OK) grouped_done = true;
+            else if (st != RP_ERR_UNSUPPORTED) return st;
+        }
+    }
+    for (int i = 0; i < N; ++i) {
+        if (hm.tn_mode[i]) {
+            rpmi::TnTcecArgs t;
+            t.A = X;
+            t.lda = dims[i];
+            t.m = hm.before[i];
+            t.n = dims[i];
+            t.p = ranks[i];
+            t.qhi = hm.pk[i].data;
+            t.qlo = nullptr;
+            t.nt_count = hm.pk[i].nt_count;
+            t.Z = W[i];
+            t.ldz = ldw[i];
+            t.status = ctx->d_status;
+            t.ksplit = hm.tn_split_k[i];
+            t.kchunk_steps = hm.tn_chunk[i];
+            t.partial = hm.tn_split_k[i] > 1 ? reinterpret_cast<float*>(base + hm.o_tnp[i]) : nullptr;
+            RP_HIP(ctx, rpmi::launch_gemm_tn_tcec(t, s));
+        } else if (hm.permuted[i]) {
+            RP_HIP(ctx, rpmi::launch_swap01(X, hm.before[i], dims[i], hm.after[i], perm, s));
+            const int64_t cols = hm.total / dims[i];
+            const rp_desc pd{perm, dims[i], cols, cols, cols, 1, 0};
+            if ((st = launch_projection(ctx, &pd, ranks[i], hm.pk[i], algo, W[i], ldw[i], s)) != RP_OK) return st;
+        } else if (!grouped_done) {
+            if ((st = launch_projection(ctx, &hm.desc[i], ranks[i], hm.pk[i], algo, W[i], ldw[i], s)) != RP_OK)
+                return st;
+        }
+    }
+    return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rp_status rp_hosvd_project(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X, const int64_t* ranks,
+                           uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* const* W, const int64_t* ldw,
+                           void* stream) {
+    rp_status st = hosvd_check(ctx, ndim, dims, X, ranks, omega_type, algo, W, "W");
+    if (st != RP_OK) return st;
+    if (!ldw) return fail(ctx, RP_ERR_INVALID_ARG, "ldw is NULL");
+    for (int i = 0; i < ndim; ++i)
+        if (ldw[i] < ranks[i]) return fail(ctx, RP_ERR_INVALID_ARG, "ldw[%d] < ranks[%d]", i, i);
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    Arena ar;
+    HosvdModes hm;
+    hosvd_plan_modes(ctx, ndim, dims, X, ranks, omega_type, algo, ar, hm);
+    if ((st = ensure_workspace(ctx, ar.used)) != RP_OK) return st;
+    return hosvd_run_projections(ctx, hm, dims, X, ranks, seed, omega_type, algo, W, ldw, s);
+}
+
+rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X, const int64_t* ranks,
+                   uint64_t seed, rp_omega_t omega_type, rp_algo_t algo, float* core, float* const* factors,
+                   void* stream) {
+    rp_status st = hosvd_check(ctx, ndim, dims, X, ranks, omega_type, algo, factors, "factors");
+    if (st != RP_OK) return st;
+    if (!core) return fail(ctx, RP_ERR_INVALID_ARG, "NULL pointer");
+    const int N = ndim;
+    hipStream_t s = (hipStream_t)stream;
+    RP_HIP(ctx, hipSetDevice(ctx->device));
+    Arena ar;
+    HosvdModes hm;
+    hosvd_plan_modes(ctx, N, dims, X, ranks, omega_type, algo, ar, hm);
+    const int64_t* after = hm.after;
+    int64_t maxr = 0, maxd = 0;
+    for (int i = 0; i < N; ++i) {
         maxr = ranks[i] > maxr ? ranks[i] : maxr;
         maxd = dims[i] > maxd ? dims[i] : maxd;
     }
@@ -1963,20 +2195,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
             tmax = e > tmax ? e : tmax;
         }
     }
-    Arena ar;
-    size_t o_pk[rpmi::kMaxGroup], o_w[rpmi::kMaxGroup];
-    rpmi::PackedOmega pk[rpmi::kMaxGroup];
-    size_t rawb = 0;
-    for (int i = 0; i < N; ++i) {
-        const int64_t cols = total / dims[i];
-        pk[i] = packed_geometry(cols, ranks[i], algo, nullptr);
-        o_pk[i] = ar.take(packed_bytes(pk[i], algo));
-        o_w[i] = ar.take((size_t)dims[i] * ranks[i] * 4);
-        const size_t rb = raw_bytes(omega_type, algo, cols, ranks[i]);
-        rawb = rb > rawb ? rb : rawb;
-    }
-    const size_t o_raw = ar.take(rawb);
-    const size_t o_perm = ar.take((size_t)perm_elems * 4);
+    size_t o_w[rpmi::kMaxGroup];
+    for (int i = 0; i < N; ++i) o_w[i] = ar.take((size_t)dims[i] * ranks[i] * 4);
     const size_t o_qd = ar.take((size_t)maxd * maxr * 8);
     const size_t o_g = ar.take((size_t)maxr * maxr * 8);
     const size_t o_x = ar.take((size_t)maxr * maxr * 8);
@@ -1994,54 +2214,12 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
     char* base = static_cast<char*>(ctx->ws);
     float* W[rpmi::kMaxGroup];
     int64_t ldw[rpmi::kMaxGroup];
-    const rp_desc* dp[rpmi::kMaxGroup];
-    float* perm = reinterpret_cast<float*>(base + o_perm);
-
-    // Algorithm 2, first loop: W_i = X_(i) Omega_i, Omega_i from stream i.
-    // Modes whose unfolding the projection cannot stream in place are first
-    // copied mode-first into one scratch tensor (one mode at a time, so those
-    // projections run separately).
     for (int i = 0; i < N; ++i) {
         W[i] = reinterpret_cast<float*>(base + o_w[i]);
         ldw[i] = ranks[i];
-        dp[i] = &desc[i];
-        const int64_t cols = total / dims[i];
-        st = cached_packed_omega(ctx, seed, (uint32_t)i, omega_type, cols, ranks[i], algo, base + o_raw, s, &pk[i]);
-        if (st == RP_ERR_UNSUPPORTED) {
-            pk[i].data = base + o_pk[i];
-            st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, pk[i],
-                             base + o_raw, s);
-        }
-        if (st != RP_OK) return st;
     }
-    bool grouped_done = false;
-    if (algo == RP_ALGO_SPLIT_F16) {
-        const rp_desc* gA[rpmi::kMaxGroup];
-        int64_t gr[rpmi::kMaxGroup], gld[rpmi::kMaxGroup];
-        rpmi::PackedOmega gpk[rpmi::kMaxGroup];
-        float* gY[rpmi::kMaxGroup];
-        int cnt = 0;
-        for (int i = 0; i < N; ++i) {
-            if (permuted[i]) continue;
-            gA[cnt] = dp[i]; gr[cnt] = ranks[i]; gld[cnt] = ldw[i]; gpk[cnt] = pk[i]; gY[cnt] = W[i];
-            ++cnt;
-        }
-        if (cnt > 1) {
-            st = launch_projection_grouped(ctx, cnt, gA, gr, gpk, gY, gld, s);
-            if (st == RP_OK) grouped_done = true;
-            else if (st != RP_ERR_UNSUPPORTED) return st;
-        }
-    }
-    for (int i = 0; i < N; ++i) {
-        if (permuted[i]) {
-            RP_HIP(ctx, rpmi::launch_swap01(X, before[i], dims[i], after[i], perm, s));
-            const int64_t cols = total / dims[i];
-            const rp_desc pd{perm, dims[i], cols, cols, cols, 1, 0};
-            if ((st = launch_projection(ctx, &pd, ranks[i], pk[i], algo, W[i], ldw[i], s)) != RP_OK) return st;
-        } else if (!grouped_done) {
-            if ((st = launch_projection(ctx, dp[i], ranks[i], pk[i], algo, W[i], ldw[i], s)) != RP_OK) return st;
-        }
-    }
+    // Algorithm 2, first loop: W_i = X_(i) Omega_i, Omega_i from stream i
+    if ((st = hosvd_run_projections(ctx, hm, dims, X, ranks, seed, omega_type, algo, W, ldw, s)) != RP_OK) return st;
     // Q_i = QR(W_i) straight into the caller's factors
     double* Qd = reinterpret_cast<double*>(base + o_qd);
     double* G = reinterpret_cast<double*>(base + o_g);

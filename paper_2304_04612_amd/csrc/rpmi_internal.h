@@ -81,14 +81,20 @@ struct GroupEntry {
     ProjArgs p;
     int64_t tiles_m, tiles_n;
     int64_t start;
+    int64_t rstart;                   // LDS-staged launches: first block of the reduction pass
 };
+// reduction-pass blocks of a problem with `tiles` output tiles and a
+// contraction split on an LDS-staged grouped launch (narrow_lds: the
+// r <= 128 form, else the wide one)
+int64_t split_group_reduce_blocks(int64_t tiles, bool narrow_lds);
 int64_t split_group_tile_m(int64_t r);
 int64_t split_group_tile_n(int64_t r);
 // `one` != NULL: a single problem passed by value (table and count unused)
+// rblocks: blocks of the reduction pass (wide grouped launches)
 hipError_t launch_project_split_f16_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                            hipStream_t s, const GroupEntry* one = nullptr);
+                                            hipStream_t s, const GroupEntry* one = nullptr, int64_t rblocks = 0);
 hipError_t launch_split_group_wide(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
-                                   hipStream_t s);
+                                   hipStream_t s, int64_t rblocks = 0);
 hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t blocks, const GroupEntry* one,
                                      hipStream_t s);
 bool split_fast_ok(const ProjArgs& a);
@@ -108,6 +114,13 @@ struct SplitPlan {
     size_t counter_bytes;
 };
 SplitPlan plan_split_f16(int64_t m, int64_t n, int64_t r, int num_cus);
+// The LDS-staged form of the narrow (r <= 128) grouped launch: its plan,
+// its row tile (the column tile is 128 as in the register-staged form) and
+// its launch.
+SplitPlan plan_split_f16_narrow_lds(int64_t m, int64_t n, int64_t r, int num_cus);
+int64_t split_group_tile_m_narrow_lds();
+hipError_t launch_split_group_narrow_lds(const GroupEntry* table, int count, int64_t blocks, int64_t rblocks,
+                                         hipStream_t s);
 
 // Scratch of the no-allocation projection entry point (one static device
 // array per device): partial sums first, then the arrival counters.  The
@@ -174,8 +187,20 @@ struct TnTcecArgs {
     float* Z = nullptr;
     int64_t ldz = 0;
     unsigned int* status = nullptr;
+    // contraction split: chunk kz of ksplit takes 32-row steps
+    // [kz kchunk_steps, (kz + 1) kchunk_steps) into partial + kz n p (ld p);
+    // a second kernel adds the chunks, in a fixed order, into Z
+    int ksplit = 1;
+    int64_t kchunk_steps = 0;
+    float* partial = nullptr;
 };
+// qlo == NULL: Q is FP16 (its lo part is zero), e.g. an FP16 Omega packed for
+// the split projection; then Z = A^T Q is the split product of eq:shgemm-3 in
+// its transposed form (two products per step instead of three).
 hipError_t launch_gemm_tn_tcec(const TnTcecArgs& t, hipStream_t s);
+// contraction split for an n x p output over m rows: about `cus` workgroups
+// (chunks of at least 16 steps); 1 if no split pays
+int plan_tn_tcec_split(int64_t m, int64_t n, int64_t p, int cus, int64_t* chunk_steps);
 // Pack a row-major FP32 W (n x r, leading dimension ldo) for the TCEC
 // kernels: FP16 hi fragments at dst.data, then the RN16(2^11 (w - hi))
 // fragments; |hi| >= 32 or a non-finite value sets `flag_bit` in *flag (the

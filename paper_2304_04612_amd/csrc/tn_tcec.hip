@@ -62,6 +62,7 @@ __device__ __forceinline__ half8 tr_operand(const _Float16* rows0, const _Float1
     return __builtin_bit_cast(half8, v);
 }
 
+template <bool QLO>
 __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs t) {
     __shared__ _Float16 ahi0[32 * kTnPitch], ahi1[32 * kTnPitch], ahi2[32 * kTnPitch];
     __shared__ _Float16 alo0[32 * kTnPitch], alo1[32 * kTnPitch], alo2[32 * kTnPitch];
@@ -89,13 +90,20 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
     };
 
     const int64_t tiles_c = (t.p + kTnBC - 1) / kTnBC;
-    const int64_t blk = tn_xcd_dense(blockIdx.x, gridDim.x);
+    const int64_t tiles = tiles_c * ((t.n + kTnBJ - 1) / kTnBJ);
+    const int64_t dense = tn_xcd_dense(blockIdx.x, gridDim.x);
+    const int kz = (int)(dense / tiles);
+    const int64_t blk = dense - kz * tiles;
     const int64_t bc = blk % tiles_c, bj = blk / tiles_c;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wc = wave & 1, wj = wave >> 1;
     const int g = lane >> 4, c16 = lane & 15;
-    const int64_t nsteps = (t.m + 31) / 32;
+    // this chunk's steps: [s0, s0 + nsteps) of the (m + 31) / 32
+    const int64_t all_steps = (t.m + 31) / 32;
+    const int64_t s0 = t.ksplit > 1 ? kz * t.kchunk_steps : 0;
+    const int64_t left = all_steps - s0;
+    const int64_t nsteps = t.ksplit > 1 ? (left < t.kchunk_steps ? left : t.kchunk_steps) : all_steps;
 
     // A loads: thread row r (0..31), float4 columns q = (tid mod 16) + 16 u
     const int r = tid >> 4;
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
     // (raw loads; rows past m and columns past n are zeroed when split, so
     // that no use of the loaded registers comes before that)
     auto load_a = [&](floatx4 (&dst)[4], int64_t step) RPMI_INLINE {
-        const int64_t i = step * 32 + r;
+        const int64_t i = (s0 + step) * 32 + r;
         const int64_t ic = i < t.m ? i : t.m - 1;
 #pragma unroll
         for (int u = 0; u < 4; ++u) dst[u] = *reinterpret_cast<const floatx4*>(acol[u] + ic * t.lda);
@@ -122,9 +130,9 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
     const int64_t qoff = (bc * 8 + wave) * 64 + lane;
     const int64_t qstep = t.nt_count * 64;
     auto load_q = [&](half8 (&dst)[2], int64_t step) RPMI_INLINE {
-        const int64_t st = step < nsteps ? step : nsteps - 1;     // past the end: never stored
+        const int64_t st = s0 + (step < nsteps ? step : nsteps - 1);   // past the end: never stored
         dst[0] = static_cast<const half8*>(t.qhi)[st * qstep + qoff];
-        dst[1] = static_cast<const half8*>(t.qlo)[st * qstep + qoff];
+        if constexpr (QLO) dst[1] = static_cast<const half8*>(t.qlo)[st * qstep + qoff];
     };
 
     floatx4 acc[4][4];
@@ -156,7 +164,7 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
         {
             _Float16* hrow = ahi_at(k) + r * kTnPitch;
             _Float16* lrow = alo_at(k) + r * kTnPitch;
-            const bool rowok = s * 32 + r < t.m;
+            const bool rowok = (s0 + s) * 32 + r < t.m;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 uint2 h, l;
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
                 *reinterpret_cast<uint2*>(lrow + col) = l;
             }
             qh_at(k)[wave * 64 + lane] = rq_at(k)[0];
-            ql_at(k)[wave * 64 + lane] = rq_at(k)[1];
+            if constexpr (QLO) ql_at(k)[wave * 64 + lane] = rq_at(k)[1];
         }
         // every wave's A rows and Q fragments of this step are in LDS
         __syncthreads();
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
 #pragma unroll
         for (int tc = 0; tc < 4; ++tc) {
             bh[tc] = qh[(wc * 4 + tc) * 64 + lane];
-            bl[tc] = ql[(wc * 4 + tc) * 64 + lane];
+            if constexpr (QLO) bl[tc] = ql[(wc * 4 + tc) * 64 + lane];
             bh2[tc] = scale_2p11(bh[tc]);
         }
         const _Float16* ah = ahi_at(k);
@@ -192,9 +200,11 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
 #pragma unroll
             for (int tc = 0; tc < 4; ++tc)
                 acc[tc][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh2[tc], xh, acc[tc][tj], 0, 0, 0);
+            if constexpr (QLO) {
 #pragma unroll
-            for (int tc = 0; tc < 4; ++tc)
-                acc[tc][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[tc], xh, acc[tc][tj], 0, 0, 0);
+                for (int tc = 0; tc < 4; ++tc)
+                    acc[tc][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[tc], xh, acc[tc][tj], 0, 0, 0);
+            }
 #pragma unroll
             for (int tc = 0; tc < 4; ++tc)
                 acc[tc][tj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[tc], xl, acc[tc][tj], 0, 0, 0);
@@ -220,8 +230,10 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
     if (any_nonfinite(acc)) atomicOr(t.status, kStatusRange);
 
     // Z[j][c .. c + 3] = 2^-11 acc: lane (g, c16) of subtile (tc, tj) holds
-    // Z^T rows c = 4g + e, column j = c16
-    const bool vec = (t.ldz & 3) == 0 && (reinterpret_cast<uintptr_t>(t.Z) & 15) == 0;
+    // Z^T rows c = 4g + e, column j = c16 (a chunk of a split: its partial)
+    float* const zb = t.ksplit > 1 ? t.partial + kz * t.n * t.p : t.Z;
+    const int64_t ldz = t.ksplit > 1 ? t.p : t.ldz;
+    const bool vec = (ldz & 3) == 0 && (reinterpret_cast<uintptr_t>(zb) & 15) == 0;
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
             const int64_t j = bj * kTnBJ + wj * 64 + tj * 16 + c16;
             const int64_t c0 = bc * kTnBC + wc * 64 + tc * 16 + 4 * g;
             if (j >= t.n) continue;
-            float* dst = t.Z + j * t.ldz + c0;
+            float* dst = zb + j * ldz + c0;
             const floatx4 v = acc[tc][tj] * 0x1p-11f;
             if (vec && c0 + 3 < t.p) {
                 *reinterpret_cast<floatx4*>(dst) = v;
@@ -241,15 +253,63 @@ __global__ __launch_bounds__(kTnThreads, 1) void gemm_tn_tcec_kernel(TnTcecArgs 
         }
 }
 
+// Z = the sum of the chunks' partials in a fixed order: lane group zg of a
+// block adds chunks zg, zg + 8, ... of 32 consecutive outputs, then the 8
+// group sums are added in group order
+__global__ __launch_bounds__(256) void tn_tcec_reduce_kernel(TnTcecArgs t) {
+    __shared__ float part[8][33];
+    const int el = threadIdx.x & 31, zg = threadIdx.x >> 5;
+    const int64_t np = t.n * t.p;
+    const int64_t e = (int64_t)blockIdx.x * 32 + el;
+    float acc = 0.0f;
+    if (e < np)
+        for (int z = zg; z < t.ksplit; z += 8) acc += t.partial[z * np + e];
+    part[zg][el] = acc;
+    __syncthreads();
+    if (zg == 0 && e < np) {
+        float sum = part[0][el];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) sum += part[q][el];
+        const int64_t j = e / t.p, c = e - j * t.p;
+        t.Z[j * t.ldz + c] = sum;
+    }
+}
+
 }  // namespace
+
+int plan_tn_tcec_split(int64_t m, int64_t n, int64_t p, int cus, int64_t* chunk_steps) {
+    const int64_t tiles = ((p + kTnBC - 1) / kTnBC) * ((n + kTnBJ - 1) / kTnBJ);
+    const int64_t steps = (m + 31) / 32;
+    *chunk_steps = steps;
+    if (tiles <= 0 || steps <= 0) return 1;
+    int64_t k = cus / tiles;
+    k = k > steps / 16 ? steps / 16 : k;
+    if (k < 2) return 1;
+    const int64_t chunk = (steps + k - 1) / k;
+    *chunk_steps = chunk;
+    return (int)((steps + chunk - 1) / chunk);
+}
 
 hipError_t launch_gemm_tn_tcec(const TnTcecArgs& t, hipStream_t s) {
     if (t.n <= 0 || t.p <= 0) return hipSuccess;
     if ((t.n & 3) || (t.lda & 3) || (reinterpret_cast<uintptr_t>(t.A) & 15)) return hipErrorInvalidValue;
     if (t.nt_count * 16 < ((t.p + kTnBC - 1) / kTnBC) * kTnBC) return hipErrorInvalidValue;
-    const int64_t blocks = ((t.p + kTnBC - 1) / kTnBC) * ((t.n + kTnBJ - 1) / kTnBJ);
+    const int64_t steps = (t.m + 31) / 32;
+    if (t.ksplit > 1 && (!t.partial || t.kchunk_steps <= 0 || (int64_t)(t.ksplit - 1) * t.kchunk_steps >= steps ||
+                         (int64_t)t.ksplit * t.kchunk_steps < steps))
+        return hipErrorInvalidValue;
+    const int64_t tiles = ((t.p + kTnBC - 1) / kTnBC) * ((t.n + kTnBJ - 1) / kTnBJ);
+    const int64_t blocks = tiles * (t.ksplit > 1 ? t.ksplit : 1);
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_tn_tcec_kernel, dim3((unsigned)blocks), dim3(kTnThreads), 0, s, t);
+    if (t.qlo)
+        hipLaunchKernelGGL(gemm_tn_tcec_kernel<true>, dim3((unsigned)blocks), dim3(kTnThreads), 0, s, t);
+    else
+        hipLaunchKernelGGL(gemm_tn_tcec_kernel<false>, dim3((unsigned)blocks), dim3(kTnThreads), 0, s, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || t.ksplit <= 1) return e;
+    const int64_t g = (t.n * t.p + 31) / 32;
+    if (g > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tn_tcec_reduce_kernel, dim3((unsigned)g), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -259,3 +259,33 @@ def test_tuning_cache_persists(tmp_path, monkeypatch):
         rp().rp_tuning_load(str(tmp_path / "missing.txt"), ctx=c2)
     for c in (c1, c2, c3):
         c.close()
+
+
+@pytest.mark.parametrize("form", ["0", "1"])
+def test_grouped_narrow_kernel_forms(form, monkeypatch):
+    """Both kernel forms of the narrow (r <= 128) 16-byte-path problems
+    (RPMI_GROUP_FORM fixes the one the autotuner would pick): grouped
+    projections within the split product's elementwise bound, and a batched
+    RSVD that recovers its planted spectra like the oracle."""
+    monkeypatch.setenv("RPMI_GROUP_FORM", form)
+    c = rp().Context(0)
+    shapes = [(300, 4096, 100), (1000, 2048, 64), (64, 512, 8), (257, 1024, 128), (700, 2048, 200)]
+    announce(f"grouped projections, narrow form {form}: {shapes}")
+    rng = np.random.default_rng(12)
+    mats = [rng.standard_normal((m, n)).astype(np.float32) for m, n, _ in shapes]
+    ys = rp().rp_project_grouped([(dev(a), r, 6, j) for j, (a, (_, _, r)) in enumerate(zip(mats, shapes))], ctx=c)
+    assert rp().rp_get_device_status(clear=True, ctx=c) == rp().RP_OK
+    for j, (a, (m, n, r)) in enumerate(zip(mats, shapes)):
+        om = omega.omega_f16(6, j, n, r)
+        ref = project.project_f64(a, om)
+        bound = (project.gamma(n + 2, U32) + U16 * U16) * project.abs_product(a, om)
+        assert np.all(np.abs(host(ys[j]).astype(np.float64) - ref) <= bound), (form, j)
+    batch = [b for b in _planted_batch(8, 66, 64, 600, 4, 20) if b[0].shape[1] % 4 == 0] or \
+        _planted_batch(3, 67, 64, 64, 4, 8)
+    outs = rp().rsvd_batched([dev(a) for a, _, _, _ in batch], [k for _, k, _, _ in batch],
+                             [s for _, _, s, _ in batch], 0, 21, "f16", ctx=c)
+    assert rp().rp_get_device_status(clear=True, ctx=c) == rp().RP_OK
+    for j, ((a, k, s, sig), (_, sv, _)) in enumerate(zip(batch, outs)):
+        _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), omega.omega_f16(21, j, a.shape[1], k + s), k, 0)
+        assert np.abs(host(sv) - sv_o).max() <= 1e-5 * sv_o[0], (form, j)
+    c.close()

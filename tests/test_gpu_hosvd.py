@@ -33,7 +33,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dims,core_dims,ranks,noise,omega_type,algo", [
-    ((64, 96, 128), (8, 6, 10), (8, 6, 10), 0.0, "f16", "split_f16"),      # grouped + permuted last mode
+    ((64, 96, 128), (8, 6, 10), (8, 6, 10), 0.0, "f16", "split_f16"),      # grouped + transposed last mode
     ((64, 96, 128), (8, 6, 10), (12, 10, 14), 1e-3, "f16", "split_f16"),   # oversampled, noisy
     ((40, 36, 64), (5, 6, 7), (5, 6, 7), 0.0, "f32", "f32"),                # FP32 baseline
     ((40, 36, 64), (5, 6, 7), (5, 6, 7), 0.0, "f16", "f32"),
@@ -66,6 +66,33 @@ def test_hosvd_matches_oracle(dims, core_dims, ranks, noise, omega_type, algo):
         assert _rel(g, g_o) < 1e-4
     else:
         assert abs(err - err_o) < 1e-3 * err_o
+
+
+@pytest.mark.parametrize("dims,ranks", [
+    ((64, 96, 128), (12, 10, 14)),     # grouped modes 1, 2; mode 3 transposed with a contraction split
+    ((300, 20), (6, 7)),               # 2-way: mode 2 transposed, no split
+    ((33, 70, 45), (4, 5, 6)),         # ragged: modes 2, 3 copied mode-first
+    ((16, 12, 64, 12), (3, 4, 5, 6)),  # 4-way: modes 1, 2 in place, mode 3 copied, mode 4 transposed
+])
+def test_hosvd_project_elementwise_bound(dims, ranks):
+    """Algorithm 2 line 2 for every mode (rp_hosvd_project): W_i within the
+    split product's elementwise bound (gamma_{n+2}(2^-24) + 2^-22)
+    |X_(i)| |Omega_i| of the FP64 oracle on the same X and Omega_i, whichever
+    route the mode takes (in place, transposed, or copied)."""
+    from oracle import project
+    announce(f"hosvd_project dims={dims} ranks={ranks}")
+    rng = np.random.default_rng(17)
+    x = (rng.standard_normal(dims) * np.exp(rng.uniform(-3, 3, dims))).astype(np.float32)
+    ws = rp().rp_hosvd_project(dev(x), ranks, 33, "f16", "split_f16")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    x64 = x.astype(np.float64)
+    for i in range(len(dims)):
+        a = ohosvd.unfold(x64, i)
+        om = omega.omega_f16(33, i, a.shape[1], ranks[i]).astype(np.float64)
+        ref = a @ om
+        bound = (project.gamma(a.shape[1] + 2, 2.0 ** -24) + 2.0 ** -22) * (np.abs(a) @ np.abs(om))
+        w = host(ws[i]).astype(np.float64)
+        assert np.all(np.abs(w - ref) <= bound), (i, float(np.max(np.abs(w - ref) / bound)))
 
 
 def test_hosvd_invalid_arguments():
@@ -122,8 +149,11 @@ def test_hosvd_full_size_vs_oracle():
       2^-22) (|X_(i)| |Omega_i|).
     * Factors: the thin QR factor with positive diag(R) is unique, and to
       first order ||dQ||_F <= sqrt(2) ||dW||_F / sigma_min(W) (perturbation
-      of the QR factorisation); rp_hosvd runs the same kernel with another
-      contraction split, so its dW is taken as at most 4x the measured one.
+      of the QR factorisation); rp_hosvd runs the same split arithmetic
+      with another summation order (modes 1 and 2: another contraction
+      split; mode 3: X streamed in place through the transposed kernel, the
+      same hi/lo split of every element against the same FP16 Omega_3), so
+      its dW is taken as at most 4x the measured one.
     * Core: ||dg||_F <= (sum_i ||dQ_i||_2) ||X||_F to first order.
     * Reconstruction: eq:qqta-acc with k = 64 and oversampling J - k = 16
       bounds E||(I - Q_i Q_i^T) X_(i)||_F^2 by (1 + 64/15) times the tail
