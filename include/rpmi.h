@@ -65,6 +65,10 @@ typedef enum rp_omega_t {
 } rp_omega_t;
 
 /* How Y = A * Omega is computed. */
+/* a_scale_exp value: a power-of-two pre-scale per row of A, chosen on the
+ * device (see rp_project) */
+#define RP_A_SCALE_AUTO_ROW 32767
+
 typedef enum rp_algo_t {
     RP_ALGO_F32 = 0,          /* plain FP32 GEMM on FP32 matrix cores (baseline form);
                                  an FP16 Omega is widened exactly to FP32 first, as
@@ -162,6 +166,19 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
  *              the FP32 normal range), so that an A whose magnitudes exceed
  *              the FP16 range (Sec. 4.2) can be brought inside it; 0 = off.
  *              |s| <= 64.  Ignored by RP_ALGO_F32 and RP_ALGO_TCEC_F16.
+ *              RP_A_SCALE_AUTO_ROW: the full FP32 exponent range (the role
+ *              of the paper's SHGEMM-TF32, Sec. 4.2, without a TF32 matrix
+ *              core): each row i gets its own s_i, chosen on the device so
+ *              that the row's largest |a| lands in [2^14, 2^15) (clamped to
+ *              [-126, 126]; 0 for an all-zero or non-finite row); Y's row i
+ *              is multiplied by 2^-s_i.  Exact scalings, so the elementwise
+ *              bound of the split product holds for any row whose entries
+ *              span fewer than about 28 binades below its maximum (smaller
+ *              ones may fall into FP16 subnormals, an error below 2^-38
+ *              of the row's maximum).  One extra read of A (the row maxima);
+ *              the projection then runs on the two-accumulator kernel.
+ *              Taken by rp_project and rsvd; other entry points return
+ *              RP_ERR_UNSUPPORTED for it.
  * With RP_ALGO_SPLIT_F16 an element of 2^s A that overflows FP16 (finite
  * |2^s a| >= 65520), or a non-finite element, sets RP_ERR_RANGE in the device
  * status word; Y is then unspecified (a NaN element leaves NaN in its own

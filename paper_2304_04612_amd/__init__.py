@@ -31,6 +31,7 @@ RP_ALGO_TCEC_F16 = 2
 
 OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16, "e4m3": RP_OMEGA_E4M3}
 ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16, "tcec_f16": RP_ALGO_TCEC_F16}
+RP_A_SCALE_AUTO_ROW = 32767   # a_scale_exp: one power-of-two pre-scale per row of A, chosen on the device
 
 
 class RpError(RuntimeError):

@@ -41,6 +41,18 @@ __device__ __forceinline__ void split_f16_body(const ProjArgs& p, int64_t bm, in
     if (p.fold_flags && p.fold_flags[((bm * T::BM) / WideCfg::BM) & (kFoldFlags - 1)] != p.fold_epoch) return;
 
     const AStream<T, VEC> as = make_astream<T, VEC>(p, bm, wm, c, g);
+    // the split's scale of this lane's rows: the caller pre-scale, or each
+    // row's own power of two
+    float ascale[T::TM];
+#pragma unroll
+    for (int tm = 0; tm < T::TM; ++tm) {
+        ascale[tm] = p.a_scale;
+        if (p.row_exp) {
+            int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + c;
+            row = row < p.m ? row : p.m - 1;
+            ascale[tm] = ldexpf(1.0f, p.row_exp[row]);
+        }
+    }
     const int64_t nsteps = as.nsteps;
     const half8* om = static_cast<const half8*>(p.omega);
 
@@ -89,7 +101,7 @@ __device__ __forceinline__ void split_f16_body(const ProjArgs& p, int64_t bm, in
                     half8 hi[T::TM], lo[T::TM];
 #pragma unroll
                     for (int tm = 0; tm < T::TM; ++tm)
-                        split8(ring[s][tm][kb][0] * p.a_scale, ring[s][tm][kb][1] * p.a_scale, hi[tm], lo[tm]);
+                        split8(ring[s][tm][kb][0] * ascale[tm], ring[s][tm][kb][1] * ascale[tm], hi[tm], lo[tm]);
 #pragma unroll
                     for (int j = 0; j < T::TN; ++j) {
                         const half8 b = lds[buf][(kb * T::NTB + wn * T::TN + j) * 64 + lane];
@@ -120,8 +132,10 @@ __device__ __forceinline__ void split_f16_body(const ProjArgs& p, int64_t bm, in
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t row = bm * T::BM + (wm * T::TM + tm) * 16 + 4 * g + e;
-                if (row < p.m && col < p.r)
-                    p.Y[row * p.ldy + col] = (acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f) * p.y_scale;
+                if (row < p.m && col < p.r) {
+                    const float ys = p.row_exp ? ldexpf(1.0f, -p.row_exp[row]) : p.y_scale;
+                    p.Y[row * p.ldy + col] = (acc_hi[tm][j][e] + acc_lo[tm][j][e] * 0x1p-11f) * ys;
+                }
             }
         }
 }
@@ -284,7 +298,48 @@ bool vector_ok(const ProjArgs& a) {
 
 }  // namespace
 
-bool split_fast_ok(const ProjArgs& a) { return vector_ok(a) && !a.two_acc && a.a_scale == 1.0f; }
+bool split_fast_ok(const ProjArgs& a) { return vector_ok(a) && !a.two_acc && a.a_scale == 1.0f && !a.row_exp; }
+
+namespace {
+
+// One wave per row: the largest |a| of the row (as the bit pattern of a
+// non-negative float), then the exponent that brings it into [2^14, 2^15).
+__global__ __launch_bounds__(256) void row_exponent_kernel(ProjArgs p, int* row_exp) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= p.m) return;
+    const float* base = p.A + row * p.s_row;
+    unsigned int mx = 0u;
+    for (int64_t k = lane; k < p.n; k += 64) {
+        const int64_t off = (k % p.k_inner) + (k / p.k_inner) * p.s_k_outer;
+        const unsigned int v = __float_as_uint(fabsf(base[off]));
+        mx = v > mx ? v : mx;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned int o = __shfl_xor(mx, d);
+        mx = o > mx ? o : mx;
+    }
+    if (lane == 0) {
+        const float amax = __uint_as_float(mx);
+        int e = 0;
+        if (amax > 0.0f && amax <= 3.4028235e38f) {       // finite, non-zero
+            e = 14 - ilogbf(amax);
+            e = e < -126 ? -126 : (e > 126 ? 126 : e);
+        }
+        row_exp[row] = e;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_row_exponents(const ProjArgs& a, int* row_exp, hipStream_t s) {
+    if (a.m <= 0) return hipSuccess;
+    const int64_t blocks = (a.m + 3) / 4;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, row_exp);
+    return hipGetLastError();
+}
 
 namespace {
 

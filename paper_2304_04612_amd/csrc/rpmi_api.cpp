@@ -571,12 +571,19 @@ rpmi::ProjArgs proj_args(rp_ctx ctx, const rp_desc* A, int64_t r, const void* om
     a.omega = omega; a.nt_count = nt_count;
     a.Y = Y; a.ldy = ldy; a.r = r;
     a.status = ctx->d_status;
-    a.a_scale = ldexpf(1.0f, a_scale_exp);
-    a.y_scale = ldexpf(1.0f, -a_scale_exp);
+    const int32_t se = a_scale_exp == RP_A_SCALE_AUTO_ROW ? 0 : a_scale_exp;
+    a.a_scale = ldexpf(1.0f, se);
+    a.y_scale = ldexpf(1.0f, -se);
     return a;
 }
 
-bool scale_exp_ok(rp_ctx ctx, int32_t s, rp_status* st) {
+// auto_row: the entry point takes RP_A_SCALE_AUTO_ROW
+bool scale_exp_ok(rp_ctx ctx, int32_t s, rp_status* st, bool auto_row = false) {
+    if (s == RP_A_SCALE_AUTO_ROW) {
+        if (auto_row) return true;
+        *st = fail(ctx, RP_ERR_UNSUPPORTED, "RP_A_SCALE_AUTO_ROW is taken by rp_project and rsvd only");
+        return false;
+    }
     if (s < -64 || s > 64) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "a_scale_exp %d outside [-64, 64]", (int)s);
         return false;
@@ -584,11 +591,21 @@ bool scale_exp_ok(rp_ctx ctx, int32_t s, rp_status* st) {
     return true;
 }
 
+// row_exp_ws: m ints of device workspace, needed with RP_A_SCALE_AUTO_ROW
 rp_status launch_projection(rp_ctx ctx, const rp_desc* A, int64_t r, const rpmi::PackedOmega& pk,
                             rp_algo_t algo, float* Y, int64_t ldy, hipStream_t s, int32_t a_scale_exp = 0,
-                            bool two_acc = false, const SplitBuffers* sb = nullptr) {
+                            bool two_acc = false, const SplitBuffers* sb = nullptr, int* row_exp_ws = nullptr) {
     rpmi::ProjArgs a = proj_args(ctx, A, r, pk.data, pk.nt_count, Y, ldy, a_scale_exp);
     a.two_acc = two_acc;
+    if (algo == RP_ALGO_SPLIT_F16 && a_scale_exp == RP_A_SCALE_AUTO_ROW) {
+        // full exponent range: every row's own power of two, then the general
+        // kernel (two accumulators)
+        if (!row_exp_ws) return fail(ctx, RP_ERR_INVALID_ARG, "no workspace for the row exponents");
+        RP_HIP(ctx, rpmi::launch_row_exponents(a, row_exp_ws, s));
+        a.row_exp = row_exp_ws;
+        RP_HIP(ctx, rpmi::launch_project_split_f16(a, s));
+        return RP_OK;
+    }
     if (algo == RP_ALGO_TCEC_F16) {
         a.a_scale = a.y_scale = 1.0f;
         if (!rpmi::split_fast_ok(a))
@@ -969,7 +986,7 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
     if (!desc_ok(ctx, A, &st)) return st;
     if (r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative r %lld", (long long)r);
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
-    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
+    if (!scale_exp_ok(ctx, a_scale_exp, &st, true)) return st;
     const int64_t m = A->rows, n = A->cols;
     if (m == 0 || r == 0) return RP_OK;
     if (!Y) return fail(ctx, RP_ERR_INVALID_ARG, "Y is NULL");
@@ -988,9 +1005,12 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
     const size_t pbytes = packed_bytes(pk, algo);
     const size_t raw_off = (pbytes + 255) & ~size_t(255);
     const size_t rb = omega ? 0 : raw_bytes(omega_type, algo, n, r);
-    if ((st = ensure_workspace(ctx, raw_off + rb)) != RP_OK) return st;
+    const size_t rx_off = (raw_off + rb + 255) & ~size_t(255);
+    const size_t rxb = a_scale_exp == RP_A_SCALE_AUTO_ROW ? (size_t)m * sizeof(int) : 0;
+    if ((st = ensure_workspace(ctx, rx_off + rxb)) != RP_OK) return st;
     pk.data = ctx->ws;
     void* raw = static_cast<char*>(ctx->ws) + raw_off;
+    int* row_exp = rxb ? reinterpret_cast<int*>(static_cast<char*>(ctx->ws) + rx_off) : nullptr;
     // a caller Omega for the split kernels is scanned; entries the single
     // accumulator cannot take route the call to the two-accumulator kernel
     const bool scan = omega && algo == RP_ALGO_SPLIT_F16;
@@ -1005,7 +1025,8 @@ rp_status rp_project(rp_ctx ctx, const rp_desc* A, int64_t r, rp_omega_t omega_t
         RP_HIP(ctx, hipStreamSynchronize(s));
         two_acc = word != 0;
     }
-    return launch_projection(ctx, A, r, pk, algo, Y, ldy, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, two_acc);
+    return launch_projection(ctx, A, r, pk, algo, Y, ldy, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, two_acc,
+                             nullptr, row_exp);
 }
 
 }  // extern "C"
@@ -1052,11 +1073,12 @@ rp_status cholqr2(rp_ctx ctx, int64_t m, int64_t p, const float* Y, int64_t ldy,
 struct RsvdScratch {
     int64_t m = 0, n = 0, k = 0, p = 0;
     size_t o_q, o_z, o_w, o_qd, o_g, o_x, o_l1, o_gp, o_mw, o_mv, o_sig, o_ord, o_ur, o_vr, o_pkw, o_pkq, o_jt, o_jf,
-        bytes;
+        o_rx, bytes;
     float *Q, *Z, *W;
     double *Qd, *G, *X, *L1, *GP, *MW, *MV, *sig, *Ur, *Vr;
     int* ord;
     int* jflags;                       // Jacobi flags (4 ints)
+    int* rowx;                         // row exponents of the automatic pre-scale (m ints)
     bool tcec_aw = false;              // power scheme's A W on the TCEC products (pkw in TCEC form)
     bool tcec_atq = false;             // A^T Q on the TCEC products (Q packed into pkq)
     const SplitBuffers* aw_sb = nullptr;   // contraction-split buffers for A W (else the context's)
@@ -1089,6 +1111,7 @@ struct RsvdScratch {
         o_pkq = ar.take(tcec_room ? packed_bytes(pkq, RP_ALGO_TCEC_F16) : 0);
         o_jt = ar.take(sizeof(rpmi::JacobiProb));
         o_jf = ar.take(4 * sizeof(int));
+        o_rx = ar.take((size_t)m * sizeof(int));
         bytes = ar.used;
         return outer.take(bytes);
     }
@@ -1111,6 +1134,7 @@ struct RsvdScratch {
         pkq.data = b + o_pkq;
         jtab = reinterpret_cast<rpmi::JacobiProb*>(b + o_jt);
         jflags = reinterpret_cast<int*>(b + o_jf);
+        rowx = reinterpret_cast<int*>(b + o_rx);
     }
 };
 
@@ -1587,7 +1611,7 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     if (!enums_ok(ctx, omega_type, algo, &st)) return st;
     if (algo == RP_ALGO_TCEC_F16)
         return fail(ctx, RP_ERR_INVALID_ARG, "the randomized algorithms project with RP_ALGO_F32 or RP_ALGO_SPLIT_F16");
-    if (!scale_exp_ok(ctx, a_scale_exp, &st)) return st;
+    if (!scale_exp_ok(ctx, a_scale_exp, &st, true)) return st;
     const rp_rsvd_problem prob{m, n, A, lda, k, oversample, U, ldu, S, VT, ldvt};
     if ((st = rsvd_check(ctx, prob, power_iters)) != RP_OK) return st;
     const RsvdPlan pl = rsvd_plan(ctx, m, n, k, oversample, omega_type, algo);
@@ -1636,7 +1660,7 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     }
     if (st != RP_OK) return st;
     if ((st = launch_projection(ctx, &dA, p, pk, algo, Y, p, s, algo == RP_ALGO_SPLIT_F16 ? a_scale_exp : 0, false,
-                                &sb)) != RP_OK)
+                                &sb, w.rowx)) != RP_OK)
         return st;
     return rsvd_after_projection(ctx, dA, prob, p, power_iters, Y, w, s);
 }

@@ -69,7 +69,15 @@ struct ProjArgs {
     // hi fragments of the FP32 right operand and `omega_lo` its FP16
     // RN16(2^11 (w - hi)) fragments, in the same order
     const void* omega_lo = nullptr;
+    // automatic per-row pre-scale (full FP32 exponent range of A): row i of
+    // A is split as 2^row_exp[i] a and row i of Y multiplied by 2^-row_exp[i]
+    // (a_scale and y_scale are then 1); general kernel only
+    const int* row_exp = nullptr;
 };
+// row_exp[i] = the power of two that brings max_k |A[i][k]| into [2^14, 2^15)
+// (clamped to [-126, 126]; 0 for an all-zero or non-finite row), over the
+// unfolding layout of `a` (its A, m, n, s_row, k_inner, s_k_outer)
+hipError_t launch_row_exponents(const ProjArgs& a, int* row_exp, hipStream_t s);
 constexpr int kFoldFlags = 4096;      // flag table of the folded split (power of two)
 
 // Several split-FP16 projections in one launch (all on the 16-byte path and
