@@ -59,9 +59,16 @@ typedef enum rp_status {
 typedef enum rp_omega_t {
     RP_OMEGA_F32 = 0,         /* FP32 Gaussian                                     */
     RP_OMEGA_F16 = 1,         /* FP16 Gaussian, exact sample of RN16(N(0,1))        */
-    RP_OMEGA_E4M3 = 2         /* FP8 e4m3fn of the FP32 Gaussian, power-of-two
+    RP_OMEGA_E4M3 = 2,        /* FP8 e4m3fn of the FP32 Gaussian, power-of-two
                                  scale per column (rp_omega_generate_e4m3); the
                                  projections take Omega8 / s_j, exact in FP16     */
+    /* Sparse random matrices of eq:sp-rand (Sec. 2.2) without their sqrt(s)
+     * factor (Sec. 3.4: only the range of Y = A Omega is used): entries in
+     * {-1, 0, +1}, +1 and -1 each with probability 1/(2s); exact in FP16 and
+     * FP32, stored like RP_OMEGA_F16 (FP16 bits). */
+    RP_OMEGA_SPARSE1 = 3,     /* s = 1: +-1 with probability 1/2 each           */
+    RP_OMEGA_SPARSE3 = 4,     /* s = 3 (Achlioptas)                             */
+    RP_OMEGA_VSPARSE = 5      /* s = sqrt(n) for an n-row Omega (very sparse)   */
 } rp_omega_t;
 
 /* How Y = A * Omega is computed. */
@@ -138,6 +145,11 @@ const char* rp_last_error(rp_ctx ctx);
  *   +0.  FP32: same cell k, position from the upper 32 bits f of the same word
  *   of the block with counter word 3 = 1:
  *   RN32(mu_{k-1} + (mu_k - mu_{k-1}) (f + 1/2) 2^-32), mu_{-1} = 0.
+ * The sparse types (FP16 bits) take the whole 64-bit word x of the same
+ * element: +1 if x < T, -1 if T <= x < 2T, 0 otherwise, with
+ * T = floor(2^64 / (2s)): 2^63 (s = 1), floor(2^64 / 6) (s = 3),
+ * floor(2^63 / sqrt(n)) = isqrt(floor(2^126 / n)) (s = sqrt(n)); the
+ * probabilities are 1/(2s) to within 2^-64.
  * n, r >= 0 (zero sizes enqueue nothing).
  */
 rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,

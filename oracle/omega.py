@@ -122,3 +122,52 @@ def omega_e4m3(seed, stream_id, n, r):
     scale = np.where(cmax > 0, np.ldexp(1.0, ex - 1), 1.0)
     codes = e4m3_encode_rne(w32 * scale[None, :])
     return codes, scale, e4m3_decode(codes) / scale[None, :]
+
+
+# ---------------------------------------------------------------- sparse Omega
+# Sec. 2.2, eq:sp-rand: Omega_ij = sqrt(s) * (+1 with probability 1/(2s),
+# 0 with probability 1 - 1/s, -1 with probability 1/(2s)), for s = 1 and 3
+# (Achlioptas) and s = sqrt(n) (very sparse, Li et al.).  Sec. 3.4 drops the
+# sqrt(s) factor (only the range of A Omega is used), so the entries are
+# -1, 0 and +1.  This build's reading of the sampling: the whole 64-bit word x
+# of element (i, j) (the same word as above) against T = floor(2^64 / (2s)):
+# +1 if x < T, -1 if T <= x < 2T, 0 otherwise.
+
+SPARSE_KINDS = ("sparse1", "sparse3", "vsparse")
+
+
+def sparse_threshold(kind, n):
+    """T = floor(2^64 / (2s)) in exact integer arithmetic; for s = sqrt(n),
+    floor(2^63 / sqrt(n)) = isqrt(floor(2^126 / n))."""
+    import math
+    if kind == "sparse1":
+        return 1 << 63
+    if kind == "sparse3":
+        return (1 << 64) // 6
+    if kind == "vsparse":
+        return math.isqrt((1 << 126) // max(int(n), 1))
+    raise ValueError(kind)
+
+
+def omega_sparse(seed, stream_id, n, r, kind):
+    """Float64 n x r matrix of entries in {-1, 0, +1}."""
+    t = sparse_threshold(kind, n)
+    x = _words(seed, stream_id, n, r, 0)
+    out = np.zeros(x.shape, dtype=np.float64)
+    if t >= (1 << 64):
+        raise ValueError("threshold out of range")
+    tt = np.uint64(t)
+    plus = x < tt
+    minus = (~plus) & ((x - tt) < tt)
+    out[plus] = 1.0
+    out[minus] = -1.0
+    return out
+
+
+def omega_sparse_f16_bits(seed, stream_id, n, r, kind):
+    """The same matrix as FP16 bit patterns (0x3C00, 0xBC00, 0)."""
+    v = omega_sparse(seed, stream_id, n, r, kind)
+    bits = np.zeros(v.shape, dtype=np.uint16)
+    bits[v > 0] = 0x3C00
+    bits[v < 0] = 0xBC00
+    return bits

@@ -25,11 +25,15 @@ RP_ERR_OMEGA_RANGE = 8
 RP_OMEGA_F32 = 0
 RP_OMEGA_F16 = 1
 RP_OMEGA_E4M3 = 2
+RP_OMEGA_SPARSE1 = 3
+RP_OMEGA_SPARSE3 = 4
+RP_OMEGA_VSPARSE = 5
 RP_ALGO_F32 = 0
 RP_ALGO_SPLIT_F16 = 1
 RP_ALGO_TCEC_F16 = 2
 
-OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16, "e4m3": RP_OMEGA_E4M3}
+OMEGA_TYPES = {"f32": RP_OMEGA_F32, "f16": RP_OMEGA_F16, "e4m3": RP_OMEGA_E4M3, "sparse1": RP_OMEGA_SPARSE1,
+               "sparse3": RP_OMEGA_SPARSE3, "vsparse": RP_OMEGA_VSPARSE}
 ALGOS = {"f32": RP_ALGO_F32, "split_f16": RP_ALGO_SPLIT_F16, "tcec_f16": RP_ALGO_TCEC_F16}
 RP_A_SCALE_AUTO_ROW = 32767   # a_scale_exp: one power-of-two pre-scale per row of A, chosen on the device
 
@@ -175,12 +179,13 @@ def desc_from_tensor(a, k_inner=None, s_k_outer=0, rows=None, cols=None, s_row=N
 
 
 def rp_omega_generate(n, r, seed, stream_id=0, omega="f16", out=None, ctx=None):
-    """Omega (n x r) for (seed, stream_id): uint16 FP16 bits or float32."""
+    """Omega (n x r) for (seed, stream_id): FP16 bits (int16) for the FP16
+    and sparse types, float32 for "f32"."""
     import torch
     ctx = ctx or default_context()
     t = OMEGA_TYPES[omega]
     if out is None:
-        out = torch.empty((n, r), dtype=torch.int16 if t == RP_OMEGA_F16 else torch.float32,
+        out = torch.empty((n, r), dtype=torch.float32 if t == RP_OMEGA_F32 else torch.int16,
                           device=f"cuda:{ctx.device}")
     ldo = out.stride(0) if out.dim() == 2 and out.numel() else r
     _check(ctx.handle, lib().rp_omega_generate(ctx.handle, seed, stream_id, n, r, t, _ptr(out),

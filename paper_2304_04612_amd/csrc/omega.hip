@@ -9,6 +9,8 @@
 // identical on any device.  FP32: the same cell k, and a position inside it
 // from the upper 32 bits of the word of the block with counter word 3 = 1;
 // one exact FP64 product, one FP64 round-to-nearest add, one RN to FP32.
+// Sparse Omega (eq:sp-rand, Sec. 2.2, without the sqrt(s) factor as Sec. 3.4
+// allows): the whole word x against one threshold T = floor(2^64 / (2s)).
 #include "rpmi_internal.h"
 
 namespace rpmi {
@@ -50,7 +52,17 @@ __device__ __forceinline__ uint32_t f16_cell(uint64_t u, const uint64_t* __restr
     return lo;
 }
 
+// Sparse Omega (eq:sp-rand without sqrt(s)): +1, -1 or 0 from the whole word.
+__device__ __forceinline__ int sparse_value(uint64_t x, uint64_t t) {
+    if (x < t) return 1;
+    return x - t < t ? -1 : 0;
+}
+
 __device__ __forceinline__ uint16_t f16_bits_from_word(uint64_t x, const OmegaTables& t) {
+    if (t.sparse_t) {
+        const int v = sparse_value(x, t.sparse_t);
+        return v == 0 ? (uint16_t)0 : (v > 0 ? (uint16_t)0x3C00u : (uint16_t)0xBC00u);
+    }
     const uint32_t k = f16_cell(x >> 1, t.thresholds, t.guide);
     return k == 0 ? (uint16_t)0 : (uint16_t)(k | ((uint32_t)(x & 1u) << 15));
 }
@@ -63,6 +75,7 @@ __device__ __forceinline__ double f16_value(uint32_t bits) {
 }
 
 __device__ __forceinline__ float f32_from_words(uint64_t x, uint64_t y, const OmegaTables& t) {
+    if (t.sparse_t) return (float)sparse_value(x, t.sparse_t);
     const uint32_t k = f16_cell(x >> 1, t.thresholds, t.guide);
     const double upper = 0.5 * (f16_value(k) + f16_value(k + 1));
     const double lower = k == 0 ? 0.0 : 0.5 * (f16_value(k - 1) + f16_value(k));

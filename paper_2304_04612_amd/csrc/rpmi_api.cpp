@@ -106,7 +106,38 @@ rp_status hip_fail(rp_ctx ctx, hipError_t e, const char* what) {
     } while (0)
 
 rpmi::OmegaTables tables(rp_ctx ctx) {
-    return rpmi::OmegaTables{ctx->d_thresholds, ctx->d_guide, ctx->table_count};
+    return rpmi::OmegaTables{ctx->d_thresholds, ctx->d_guide, ctx->table_count, 0};
+}
+
+bool sparse_type(rp_omega_t type) {
+    return type == RP_OMEGA_SPARSE1 || type == RP_OMEGA_SPARSE3 || type == RP_OMEGA_VSPARSE;
+}
+
+// Threshold of a sparse Omega with n rows: floor(2^64 / (2s)).
+uint64_t sparse_threshold(rp_omega_t type, int64_t n) {
+    if (type == RP_OMEGA_SPARSE1) return uint64_t(1) << 63;
+    if (type == RP_OMEGA_SPARSE3) return ~uint64_t(0) / 6;   // floor((2^64 - 1) / 6) = floor(2^64 / 6)
+    // s = sqrt(n): floor(2^63 / sqrt(n)) = isqrt(floor(2^126 / n))
+    const unsigned __int128 q = ((unsigned __int128)1 << 126) / (unsigned __int128)(n > 0 ? n : 1);
+    uint64_t x = (uint64_t)1 << 63;                           // isqrt(q) < 2^63 for q < 2^126
+    if (q < ((unsigned __int128)1 << 126)) {
+        // Newton from above, integer
+        unsigned __int128 y = (unsigned __int128)1 << 63;
+        while (true) {
+            const unsigned __int128 z = (y + q / y) >> 1;
+            if (z >= y) break;
+            y = z;
+        }
+        x = (uint64_t)y;
+    }
+    return x;
+}
+
+// The generator tables for Omega of `type` with n rows.
+rpmi::OmegaTables tables(rp_ctx ctx, rp_omega_t type, int64_t n) {
+    rpmi::OmegaTables t = tables(ctx);
+    if (sparse_type(type)) t.sparse_t = sparse_threshold(type, n);
+    return t;
 }
 
 // Grow the context workspace to at least `bytes`.  Growing synchronises the
@@ -317,13 +348,13 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id, int64
     if (n < 0 || r < 0) return fail(ctx, RP_ERR_INVALID_ARG, "negative size (n %lld, r %lld)", (long long)n, (long long)r);
     if (type == RP_OMEGA_E4M3)
         return fail(ctx, RP_ERR_INVALID_ARG, "the e4m3 Omega comes with column scales: use rp_omega_generate_e4m3");
-    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32)
+    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32 && !sparse_type(type))
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)type);
     if (n == 0 || r == 0) return RP_OK;
     if (!omega) return fail(ctx, RP_ERR_INVALID_ARG, "omega is NULL");
     if (ldo < r) return fail(ctx, RP_ERR_INVALID_ARG, "ldo %lld < r %lld", (long long)ldo, (long long)r);
     RP_HIP(ctx, hipSetDevice(ctx->device));
-    RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, type == RP_OMEGA_F32,
+    RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx, type, n), seed, stream_id, n, r, type == RP_OMEGA_F32,
                                             omega, ldo, (hipStream_t)stream));
     return RP_OK;
 }
@@ -394,7 +425,7 @@ size_t packed_bytes(const rpmi::PackedOmega& pk, rp_algo_t algo) {
 }
 
 bool enums_ok(rp_ctx ctx, rp_omega_t type, rp_algo_t algo, rp_status* st) {
-    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32 && type != RP_OMEGA_E4M3) {
+    if (type != RP_OMEGA_F16 && type != RP_OMEGA_F32 && type != RP_OMEGA_E4M3 && !sparse_type(type)) {
         *st = fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)type);
         return false;
     }
@@ -446,7 +477,7 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
     }
     if (omega) {
         const rpmi::OmegaSrc src = type == RP_OMEGA_F32 ? rpmi::OmegaSrc::F32
-                                 : type == RP_OMEGA_F16 ? rpmi::OmegaSrc::F16 : rpmi::OmegaSrc::E4M3;
+                                 : type == RP_OMEGA_E4M3 ? rpmi::OmegaSrc::E4M3 : rpmi::OmegaSrc::F16;
         if (src == rpmi::OmegaSrc::E4M3 && !col_scale)
             return fail(ctx, RP_ERR_INVALID_ARG, "a caller e4m3 Omega needs its col_scale");
         RP_HIP(ctx, rpmi::launch_pack_omega(omega, src, col_scale, n, r, ldo, pk, dst_f32, dst_f32 ? nullptr : flag,
@@ -466,11 +497,11 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
         return RP_OK;
     }
     if (algo == RP_ALGO_SPLIT_F16) {
-        RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx), seed, stream_id, n, r, pk, s));
+        RP_HIP(ctx, rpmi::launch_omega_packed_f16(tables(ctx, type, n), seed, stream_id, n, r, pk, s));
         return RP_OK;
     }
     const bool src_f32 = type == RP_OMEGA_F32;
-    RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx), seed, stream_id, n, r, src_f32, scratch, r, s));
+    RP_HIP(ctx, rpmi::launch_omega_rowmajor(tables(ctx, type, n), seed, stream_id, n, r, src_f32, scratch, r, s));
     RP_HIP(ctx, rpmi::launch_pack_omega(scratch, src_f32 ? rpmi::OmegaSrc::F32 : rpmi::OmegaSrc::F16, nullptr, n, r, r,
                                         pk, true, nullptr, 0, nullptr, s));
     return RP_OK;
@@ -1694,7 +1725,7 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
                              void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
-    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_E4M3)
+    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_E4M3 && !sparse_type(omega_type))
         return fail(ctx, RP_ERR_UNSUPPORTED, "grouped projections take an FP16 or e4m3 Omega");
     rp_status st;
     for (int32_t g = 0; g < count; ++g) {
@@ -1746,7 +1777,8 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                        uint64_t seed, rp_omega_t omega_type, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
     if (count < 0 || (count > 0 && !probs)) return fail(ctx, RP_ERR_INVALID_ARG, "invalid problem list");
-    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_F32 && omega_type != RP_OMEGA_E4M3)
+    if (omega_type != RP_OMEGA_F16 && omega_type != RP_OMEGA_F32 && omega_type != RP_OMEGA_E4M3 &&
+        !sparse_type(omega_type))
         return fail(ctx, RP_ERR_INVALID_ARG, "unknown omega type %d", (int)omega_type);
     const rp_algo_t algo = omega_type == RP_OMEGA_F32 ? RP_ALGO_F32 : RP_ALGO_SPLIT_F16;
     rp_status st;

@@ -16,6 +16,9 @@ struct OmegaTables {
     const uint64_t* thresholds;       // device, count entries
     const uint32_t* guide;            // device, kGuideSize entries
     int count;
+    // 0: the Gaussian; else a sparse Omega of entries in {-1, 0, +1}: +1 for
+    // a word x < sparse_t, -1 for sparse_t <= x < 2 sparse_t, else 0
+    uint64_t sparse_t = 0;
 };
 
 // ---------------------------------------------------------------- packed Omega
