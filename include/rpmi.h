@@ -170,7 +170,7 @@ rp_status rp_omega_generate(rp_ctx ctx, uint64_t seed, uint32_t stream_id,
  *              two column scales of rp_omega_generate_e4m3; the projection
  *              takes Omega8[i][j] / s_j (exact in FP16 for s_j in
  *              [2^-7, 2^15]).  Ignored otherwise (may be NULL).
- *   algo       RP_ALGO_SPLIT_F16 (needs an FP16 or e4m3 Omega), RP_ALGO_TCEC_F16
+ *   algo       RP_ALGO_SPLIT_F16 (needs an FP16, e4m3 or sparse Omega), RP_ALGO_TCEC_F16
  *              (needs an FP32 Omega and A on the 16-byte path, otherwise
  *              RP_ERR_UNSUPPORTED) or RP_ALGO_F32.
  *   a_scale_exp  s: the split takes 2^s A instead of A and the epilogue
@@ -366,12 +366,14 @@ typedef struct {
 } rp_project_problem;
 
 /*
- * Several split-FP16 projections (Sec. 4.1) of independent shapes: the
- * problems whose A is on the 16-byte path go out in one grouped launch per
+ * Several split-FP16 projections (Sec. 4.1) of independent shapes in grouped
+ * launches: the problems whose A is on the 16-byte path in one launch per
  * column width (r <= 128, r > 128), each problem's contraction split planned
- * for its share of the compute units; the others are launched one by one.
- * omega_type must be RP_OMEGA_F16.  probs: host array of count problems,
- * read during the call.  Same device conditions as rp_project.
+ * for its share of the compute units (see the autotuner below); the others
+ * in one launch of the general kernel per column width, longest
+ * contraction first.  omega_type: RP_OMEGA_F16, RP_OMEGA_E4M3 or a sparse
+ * type; a_scale_exp of a problem in [-64, 64].  probs: host array of count
+ * problems, read during the call.  Same device conditions as rp_project.
  */
 rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem* probs,
                              rp_omega_t omega_type, void* stream);
@@ -391,8 +393,8 @@ typedef struct {
 
 /*
  * Many randomized SVDs (Algorithm 1) of different shapes in one call:
- * Omega_j from (seed, stream_id = j); RP_OMEGA_F16 takes the split-FP16
- * projection, RP_OMEGA_F32 the FP32 one.  The projections of all problems go
+ * Omega_j from (seed, stream_id = j); RP_OMEGA_F16, RP_OMEGA_E4M3 and the
+ * sparse types take the split-FP16 projection, RP_OMEGA_F32 the FP32 one.  The projections of all problems go
  * out in grouped launches whose contraction split is tuned once per
  * problem-shape signature (the grouped projection is timed at a few
  * compute-unit shares; the fastest is kept in the context).  The whole
