@@ -36,16 +36,16 @@ __device__ __forceinline__ int find_job(const int64_t* starts, int count, int64_
     return lo;
 }
 
-template <class TA, class TB, class TC>
+template <class TA, class TB, class TC, bool ACC32 = false>
 __global__ __launch_bounds__(256) void gemm_acc64_group_kernel(const GemmJob* __restrict__ jobs,
                                                                const int64_t* __restrict__ starts, int count) {
     const int64_t blk = blockIdx.x;
     const GemmJob J = jobs[find_job(starts, count, blk)];
     const int64_t local = blk - J.start;
     const int64_t ti = local / J.tiles_n, tj = local % J.tiles_n;
-    gemm64_tile<TA, TB, TC>(J.M, J.N, J.K, J.alpha, static_cast<const TA*>(J.a), J.sam, J.sak,
-                            static_cast<const TB*>(J.b), J.sbk, J.sbn, J.beta, static_cast<TC*>(J.c), J.scm, J.scn,
-                            ti * GT, tj * GT);
+    gemm64_tile<TA, TB, TC, false, ACC32>(J.M, J.N, J.K, J.alpha, static_cast<const TA*>(J.a), J.sam, J.sak,
+                                          static_cast<const TB*>(J.b), J.sbk, J.sbn, J.beta, static_cast<TC*>(J.c),
+                                          J.scm, J.scn, ti * GT, tj * GT);
 }
 
 // G = Y^T Y per job: block b of the job is (kz, t) with t an upper-triangle
@@ -311,6 +311,17 @@ hipError_t gemm_acc64_group(const GemmJob* jobs, const int64_t* starts, int coun
                        count);
     return hipGetLastError();
 }
+
+template <class TA, class TB, class TC>
+hipError_t gemm_f32_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_acc64_group_kernel<TA, TB, TC, true>), dim3((unsigned)blocks), dim3(256), 0, s, jobs,
+                       starts, count);
+    return hipGetLastError();
+}
+
+template hipError_t gemm_f32_group<float, double, float>(const GemmJob*, const int64_t*, int, int64_t, hipStream_t);
 
 template hipError_t gemm_acc64_group<float, float, double>(const GemmJob*, const int64_t*, int, int64_t, hipStream_t);
 template hipError_t gemm_acc64_group<double, double, double>(const GemmJob*, const int64_t*, int, int64_t,

@@ -47,6 +47,17 @@ __global__ __launch_bounds__(256) void gemm_acc64_kernel(
                             c + blockIdx.z * scb, scm, scn, blockIdx.y * (int64_t)GT, blockIdx.x * (int64_t)GT);
 }
 
+// the same tiling in FP32 (FP32 MFMA, FP32 accumulation)
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const TA* __restrict__ a, int64_t sam, int64_t sak,
+    const TB* __restrict__ b, int64_t sbk, int64_t sbn, double beta, TC* __restrict__ c, int64_t scm,
+    int64_t scn, int64_t sab, int64_t sbb, int64_t scb) {
+    gemm64_tile<TA, TB, TC, false, true>(M, N, K, alpha, a + blockIdx.z * sab, sam, sak, b + blockIdx.z * sbb, sbk,
+                                         sbn, beta, c + blockIdx.z * scb, scm, scn, blockIdx.y * (int64_t)GT,
+                                         blockIdx.x * (int64_t)GT);
+}
+
 // ---------------------------------------------------------------- Cholesky
 // Factor the nb x nb diagonal block at (k, k) in place (lower), in LDS.
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -613,6 +624,47 @@ hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a
                       hipStream_t s) {
     return gemm_acc64_batched<TA, TB, TC>(M, N, K, alpha, a, sam, sak, 0, b, sbk, sbn, 0, beta, c, scm, scn, 0, 1, s);
 }
+
+template <class TA, class TB, class TC>
+hipError_t gemm_f32(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                    const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
+                    hipStream_t s) {
+    return gemm_f32_batched<TA, TB, TC>(M, N, K, alpha, a, sam, sak, 0, b, sbk, sbn, 0, beta, c, scm, scn, 0, 1, s);
+}
+
+template <class TA, class TB, class TC>
+hipError_t gemm_f32_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                            int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
+                            int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const int64_t gx = (N + GT - 1) / GT, gm = (M + GT - 1) / GT;
+    if (gx > 0x7FFFFFFF) return hipErrorInvalidValue;
+    for (int64_t z0 = 0; z0 < batch; z0 += 65535) {
+        const int64_t nb = batch - z0 < 65535 ? batch - z0 : 65535;
+        for (int64_t y0 = 0; y0 < gm; y0 += 65535) {
+            const int64_t ny = gm - y0 < 65535 ? gm - y0 : 65535;
+            const int64_t r0 = y0 * GT;
+            dim3 grid((unsigned)gx, (unsigned)ny, (unsigned)nb);
+            hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, TC>), grid, dim3(256), 0, s, M - r0, N, K, alpha,
+                               a + z0 * sab + r0 * sam, sam, sak, b + z0 * sbb, sbk, sbn, beta,
+                               c + z0 * scb + r0 * scm, scm, scn, sab, sbb, scb);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template hipError_t gemm_f32<float, double, float>(int64_t, int64_t, int64_t, double, const float*, int64_t, int64_t,
+                                                   const double*, int64_t, int64_t, double, float*, int64_t, int64_t,
+                                                   hipStream_t);
+template hipError_t gemm_f32<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t, int64_t,
+                                                  const float*, int64_t, int64_t, double, float*, int64_t, int64_t,
+                                                  hipStream_t);
+template hipError_t gemm_f32_batched<float, float, float>(int64_t, int64_t, int64_t, double, const float*, int64_t,
+                                                          int64_t, int64_t, const float*, int64_t, int64_t, int64_t,
+                                                          double, float*, int64_t, int64_t, int64_t, int64_t,
+                                                          hipStream_t);
 
 template <class TA, class TB, class TC>
 hipError_t gemm_acc64_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,

@@ -1254,8 +1254,9 @@ rp_status rsvd_after_svd(rp_ctx ctx, const rp_rsvd_problem& q, int64_t p, const 
     const int64_t m = q.m, n = q.n, k = q.k;
     RP_HIP(ctx, rpmi::svd_finish(w.MW, w.MV, (int)p, (int)k, w.sig, w.ord, w.Ur, w.Vr, s));
     RP_HIP(ctx, hipMemcpyAsync(q.S, w.sig, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(m, k, p, 1.0, w.Q, p, 1, w.Ur, k, 1, 0.0, q.U, q.ldu, 1, s)));
-    RP_HIP(ctx, (rpmi::gemm_acc64<float, double, float>(n, k, p, 1.0, w.W, p, 1, w.Vr, k, 1, 0.0, q.VT, 1, q.ldvt, s)));
+    // Algorithm 1 line 5 in FP32 (U_r, V_r rounded to FP32)
+    RP_HIP(ctx, (rpmi::gemm_f32<float, double, float>(m, k, p, 1.0, w.Q, p, 1, w.Ur, k, 1, 0.0, q.U, q.ldu, 1, s)));
+    RP_HIP(ctx, (rpmi::gemm_f32<float, double, float>(n, k, p, 1.0, w.W, p, 1, w.Vr, k, 1, 0.0, q.VT, 1, q.ldvt, s)));
     return RP_OK;
 }
 
@@ -1607,8 +1608,13 @@ FinishGroup build_finish_group(AuxImage& im, const rp_rsvd_problem* probs, const
 
 rp_status run_finish_group(rp_ctx ctx, const FinishGroup& F, char* aux, hipStream_t s) {
     RP_HIP(ctx, rpmi::svd_finish_group(reinterpret_cast<const rpmi::SvdJob*>(aux + F.svd), F.count, F.max_elems, s));
-    RP_HIP(ctx, (run_gemm_stage<float, double, float>(F.u, aux, s)));
-    RP_HIP(ctx, (run_gemm_stage<float, double, float>(F.vt, aux, s)));
+    // Algorithm 1 line 5 in FP32 (U_r, V_r rounded to FP32)
+    RP_HIP(ctx, (rpmi::gemm_f32_group<float, double, float>(reinterpret_cast<const rpmi::GemmJob*>(aux + F.u.jobs),
+                                                            reinterpret_cast<const int64_t*>(aux + F.u.starts),
+                                                            F.u.count, F.u.blocks, s)));
+    RP_HIP(ctx, (rpmi::gemm_f32_group<float, double, float>(reinterpret_cast<const rpmi::GemmJob*>(aux + F.vt.jobs),
+                                                            reinterpret_cast<const int64_t*>(aux + F.vt.starts),
+                                                            F.vt.count, F.vt.blocks, s)));
     return RP_OK;
 }
 
@@ -2297,8 +2303,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
         float* out = i == N - 1 ? core : bufs[i & 1];
         const int64_t J = ranks[i], I = dims[i], P = after[i];
         if (P == 1) {
-            RP_HIP(ctx, (rpmi::gemm_acc64<float, float, float>(lead, J, I, 1.0, T, I, 1, factors[i], J, 1, 0.0, out, J,
-                                                                1, s)));
+            RP_HIP(ctx, (rpmi::gemm_f32<float, float, float>(lead, J, I, 1.0, T, I, 1, factors[i], J, 1, 0.0, out, J, 1,
+                                                              s)));
         } else if (lead == 1 && core_tcec) {
             // out (J x P) = (T^T Q_i)^T: Z = T^T Q_i (P x J, into the other
             // buffer, free until the next mode) on the TCEC products, then
@@ -2311,8 +2317,8 @@ rp_status rp_hosvd(rp_ctx ctx, int32_t ndim, const int64_t* dims, const float* X
             // out (J x P) = Q_i^T T: the A^T Q form on FP32 MFMA
             RP_HIP(ctx, rpmi::gemm_tn_f32(J, P, I, factors[i], J, T, P, out, P, s));
         } else {
-            RP_HIP(ctx, (rpmi::gemm_acc64_batched<float, float, float>(J, P, I, 1.0, factors[i], 1, J, 0, T, P, 1,
-                                                                        I * P, 0.0, out, P, 1, J * P, lead, s)));
+            RP_HIP(ctx, (rpmi::gemm_f32_batched<float, float, float>(J, P, I, 1.0, factors[i], 1, J, 0, T, P, 1,
+                                                                      I * P, 0.0, out, P, 1, J * P, lead, s)));
         }
         T = out;
         lead *= J;

@@ -226,6 +226,17 @@ hipError_t launch_fill_f32(float* y, int64_t rows, int64_t cols, int64_t ld, flo
 hipError_t launch_fill_u32(unsigned int* p, int64_t count, unsigned int v, hipStream_t s);
 
 // ---------------------------------------------------------------- linalg.hip
+// The same products as gemm_acc64 below with FP32 operands, FP32 MFMA and
+// FP32 accumulation (B in FP64 is rounded to FP32 as it is loaded): the
+// products outside CholeskyQR2 and the small SVD (U, V^T, the RP-HOSVD core).
+template <class TA, class TB, class TC>
+hipError_t gemm_f32(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                    const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
+                    hipStream_t s);
+template <class TA, class TB, class TC>
+hipError_t gemm_f32_batched(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
+                            int64_t sab, const TB* b, int64_t sbk, int64_t sbn, int64_t sbb, double beta, TC* c,
+                            int64_t scm, int64_t scn, int64_t scb, int64_t batch, hipStream_t s);
 template <class TA, class TB, class TC>
 hipError_t gemm_acc64(int64_t M, int64_t N, int64_t K, double alpha, const TA* a, int64_t sam, int64_t sak,
                       const TB* b, int64_t sbk, int64_t sbn, double beta, TC* c, int64_t scm, int64_t scn,
@@ -297,6 +308,9 @@ int64_t gemm_group_tiles(int64_t M, int64_t N);
 int64_t gemm_group_tiles_n(int64_t N);
 template <class TA, class TB, class TC>
 hipError_t gemm_acc64_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s);
+// the FP32 form (FP32 MFMA and accumulation) of the same jobs
+template <class TA, class TB, class TC>
+hipError_t gemm_f32_group(const GemmJob* jobs, const int64_t* starts, int count, int64_t blocks, hipStream_t s);
 
 struct GramJob {                      // G (p x p, FP64) = Y^T Y, Y (R x p, ld ldy, FP32 or FP64)
     const void* y;
