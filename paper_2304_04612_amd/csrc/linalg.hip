@@ -400,6 +400,27 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacobiProb* tab
 // sweep, so a sweep does at least the rotations of a column sweep, with
 // p / 8 - 1 launches instead of p - 1.  A block paired with the padding block
 // (odd block count) or a partial last block just has fewer columns.
+// base[vid[i] n + r] = sum_j Qm[i][j] x[u][j] for the rows r = tid + 256 u < n
+template <int JV, int NR>
+__device__ __forceinline__ void jacobi_apply_rows(const double (&Qm)[JV][JV + 1], const int (&vid)[JV],
+                                                  const double (&x)[NR][JV], double* base, int n, int tid) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int r = tid + 256 * u;
+        if (r >= n) continue;
+#pragma unroll
+        for (int i = 0; i < JV; ++i) {
+            if (vid[i] < 0) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < JV; ++j) acc += Qm[i][j] * x[u][j];
+            base[(int64_t)vid[i] * n + r] = acc;
+        }
+    }
+}
+
+// NR: rows per thread of the W and V updates (n <= 256 NR)
+template <int NR>
 __global__ __launch_bounds__(256) void jacobi_block_round_kernel(const JacobiProb* tab, int count, int total_bpairs,
                                                                  int round, int sweep, double tol) {
     typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -432,6 +453,21 @@ __global__ __launch_bounds__(256) void jacobi_block_round_kernel(const JacobiPro
     }
     if (tid == 0) rot_any = 0;
     __syncthreads();
+
+    // V's 16 columns of this thread's rows (up to NR per thread; NR <= 2),
+    // loaded now so that their latency hides under the Gram and the inner
+    // sweep; the update below takes W from memory and V from these registers
+    // (with NR > 2 the registers would cost occupancy: V is loaded there too)
+    constexpr bool PREV = NR <= 2;
+    double xv[PREV ? NR : 1][JV];
+    if constexpr (PREV) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int r = tid + 256 * u;
+#pragma unroll
+            for (int j = 0; j < JV; ++j) xv[u][j] = (r < n && vid[j] >= 0) ? P.V[(int64_t)vid[j] * n + r] : 0.0;
+        }
+    }
 
     // H = Wp Wp^T over the n rows: wave w takes rows [w R, (w + 1) R); lane l
     // holds W[vid[l mod 16]][r] for r = l / 16 + 4 s, which is both MFMA
@@ -511,30 +547,19 @@ __global__ __launch_bounds__(256) void jacobi_block_round_kernel(const JacobiPro
     if (tid == 0) P.flags[1 + (sweep & 1)] = 1;
 
     // W_new[i][r] = sum_j Qm[i][j] W[j][r] (and V), each thread its own rows r
-    // (n <= 1024: up to 4 per thread, all loaded before any is used)
-    for (int which = 0; which < 2; ++which) {
+    // (up to NR per thread, all loaded before any is used)
+    for (int which = 0; which < (PREV ? 1 : 2); ++which) {
         double* base = which ? P.V : P.W;
-        double x[4][JV];
+        double x[NR][JV];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NR; ++u) {
             const int r = tid + 256 * u;
 #pragma unroll
             for (int j = 0; j < JV; ++j) x[u][j] = (r < n && vid[j] >= 0) ? base[(int64_t)vid[j] * n + r] : 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = tid + 256 * u;
-            if (r >= n) continue;
-#pragma unroll
-            for (int i = 0; i < JV; ++i) {
-                if (vid[i] < 0) continue;
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < JV; ++j) acc += Qm[i][j] * x[u][j];
-                base[(int64_t)vid[i] * n + r] = acc;
-            }
-        }
+        jacobi_apply_rows(Qm, vid, x, base, n, tid);
     }
+    if constexpr (PREV) jacobi_apply_rows(Qm, vid, xv, P.V, n, tid);
 }
 
 __global__ void set_jacobi_prob_kernel(JacobiProb* dst, JacobiProb v) {
@@ -843,9 +868,15 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
     if (block) max_sweeps += 8;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int round = 0; round < max_m - 1; ++round) {
-            if (block)
-                hipLaunchKernelGGL(jacobi_block_round_kernel, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab, count,
-                                   total_bpairs, round, sweep, btol);
+            if (block && max_n <= 256)
+                hipLaunchKernelGGL(jacobi_block_round_kernel<1>, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab,
+                                   count, total_bpairs, round, sweep, btol);
+            else if (block && max_n <= 512)
+                hipLaunchKernelGGL(jacobi_block_round_kernel<2>, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab,
+                                   count, total_bpairs, round, sweep, btol);
+            else if (block)
+                hipLaunchKernelGGL(jacobi_block_round_kernel<4>, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab,
+                                   count, total_bpairs, round, sweep, btol);
             else if (total_pairs >= kJacobiWavePairs)
                 hipLaunchKernelGGL(jacobi_round_kernel<true>, dim3((unsigned)((total_pairs + 3) / 4)), dim3(256), 0, s,
                                    tab, count, total_pairs, round, sweep, tol);
