@@ -516,8 +516,12 @@ rp_status fill_packed(rp_ctx ctx, uint64_t seed, uint32_t stream_id, const void*
 // cache.
 constexpr size_t kOmegaCacheBytes = size_t(1) << 30;
 
+// keep_after: entries used after this tick (by the caller's current call,
+// whose kernels may still read them) are never evicted; when the new Omega
+// does not fit without them, RP_ERR_UNSUPPORTED (nothing done).
 rp_status cached_packed_omega(rp_ctx ctx, uint64_t seed, uint32_t stream_id, rp_omega_t type, int64_t n, int64_t r,
-                              rp_algo_t algo, void* scratch, hipStream_t s, rpmi::PackedOmega* pk) {
+                              rp_algo_t algo, void* scratch, hipStream_t s, rpmi::PackedOmega* pk,
+                              uint64_t keep_after) {
     *pk = packed_geometry(n, r, algo, nullptr);
     const size_t bytes = packed_bytes(*pk, algo);
     for (auto& e : ctx->omega_cache)
@@ -529,11 +533,18 @@ rp_status cached_packed_omega(rp_ctx ctx, uint64_t seed, uint32_t stream_id, rp_
         }
     if (bytes == 0 || bytes > kOmegaCacheBytes) return RP_ERR_UNSUPPORTED;
     if (ctx->omega_cache_bytes + bytes > kOmegaCacheBytes) {
+        size_t evictable = 0;
+        for (const auto& e : ctx->omega_cache)
+            if (e.last_use <= keep_after) evictable += e.bytes;
+        if (ctx->omega_cache_bytes - evictable + bytes > kOmegaCacheBytes) return RP_ERR_UNSUPPORTED;
         RP_HIP(ctx, hipDeviceSynchronize());
         while (ctx->omega_cache_bytes + bytes > kOmegaCacheBytes) {
-            size_t lru = 0;
-            for (size_t i = 1; i < ctx->omega_cache.size(); ++i)
-                if (ctx->omega_cache[i].last_use < ctx->omega_cache[lru].last_use) lru = i;
+            size_t lru = ctx->omega_cache.size();
+            for (size_t i = 0; i < ctx->omega_cache.size(); ++i)
+                if (ctx->omega_cache[i].last_use <= keep_after &&
+                    (lru == ctx->omega_cache.size() || ctx->omega_cache[i].last_use < ctx->omega_cache[lru].last_use))
+                    lru = i;
+            if (lru == ctx->omega_cache.size()) return RP_ERR_UNSUPPORTED;   // not reached (checked above)
             RP_HIP(ctx, hipFree(ctx->omega_cache[lru].data));
             ctx->omega_cache_bytes -= ctx->omega_cache[lru].bytes;
             ctx->omega_cache.erase(ctx->omega_cache.begin() + lru);
@@ -1690,7 +1701,7 @@ rp_status rsvd(rp_ctx ctx, int64_t m, int64_t n, const float* A, int64_t lda, in
     // generated into the workspace when it does not fit the cache or the
     // caller's workspace rules out allocation)
     st = work ? RP_ERR_UNSUPPORTED
-              : cached_packed_omega(ctx, seed, 0, omega_type, n, p, algo, base + pl.o_raw, s, &pk);
+              : cached_packed_omega(ctx, seed, 0, omega_type, n, p, algo, base + pl.o_raw, s, &pk, ctx->omega_tick);
     if (st == RP_ERR_UNSUPPORTED) {
         pk.data = base + pl.o_pk;
         st = fill_packed(ctx, seed, 0, nullptr, 0, nullptr, omega_type, n, p, algo, pk, base + pl.o_raw, s);
@@ -2148,10 +2159,12 @@ rp_status hosvd_run_projections(rp_ctx ctx, HosvdModes& hm, const int64_t* dims,
     char* base = static_cast<char*>(ctx->ws);
     float* perm = reinterpret_cast<float*>(base + hm.o_perm);
     rp_status st;
+    // the Omega_i of this call stay in the cache until all of them are placed
+    const uint64_t call_tick = ctx->omega_tick;
     for (int i = 0; i < N; ++i) {
         const int64_t cols = hm.total / dims[i];
         st = cached_packed_omega(ctx, seed, (uint32_t)i, omega_type, cols, ranks[i], algo, base + hm.o_raw, s,
-                                 &hm.pk[i]);
+                                 &hm.pk[i], call_tick);
         if (st == RP_ERR_UNSUPPORTED) {
             hm.pk[i].data = base + hm.o_pk[i];
             st = fill_packed(ctx, seed, (uint32_t)i, nullptr, 0, nullptr, omega_type, cols, ranks[i], algo, hm.pk[i],

@@ -249,3 +249,20 @@ def test_hosvd_omega_cache_repeat():
     g_o, qs_o = _oracle(x, ranks, 92, "f16")
     rec, rec_o = ohosvd.reconstruct(g3, q3), ohosvd.reconstruct(g_o, qs_o)
     assert _rel(rec, rec_o) < 1e-3
+
+
+def test_hosvd_more_than_65535_column_tiles():
+    """4 x 2048 x 2048 with J = (4, 8, 8): the first mode's unfolding has
+    4,194,304 columns (65,536 tiles of 64), past one grid dimension's limit.
+    Properties that hold at any size (the oracle's Omega of 4.2M rows takes
+    minutes on the host): orthonormal factors and exact recovery of the
+    planted Tucker tensor of rank (2, 3, 3)."""
+    dims, core_dims, ranks = (4, 2048, 2048), (2, 3, 3), (4, 8, 8)
+    announce(f"hosvd dims={dims} ranks={ranks} (P > 65535 * 64)")
+    x = synth.np_tucker(dims, core_dims, np.random.default_rng(71), noise_std=0.0)
+    g, qs, st = _gpu(x, ranks, 12, "f16", "split_f16")
+    assert st == rp().RP_OK
+    for i in range(3):
+        assert np.abs(qs[i].T @ qs[i] - np.eye(ranks[i])).max() < 1e-5, i
+    rec = ohosvd.reconstruct(g, qs)
+    assert _rel(rec, x.astype(np.float64)) < 5e-5

@@ -139,3 +139,26 @@ def test_rsvd_full_size_vs_fp64_oracle():
     err = np.abs(sv - sig64)
     print(f"max |sigma - sigma64| {err.max():.3e} (bound {tol:.3e}), max relative {(err / sig64).max():.3e}")
     assert err.max() <= tol
+
+
+def test_rsvd_taller_than_65535_row_tiles():
+    """m = 4,200,000 rows (65,625 tiles of 64, past one grid dimension's
+    limit for the tall products: CholeskyQR2's Q = Y R^-1, U = Q U_r), n = 64,
+    planted rank 6: the planted singular values recovered and U orthonormal
+    (properties that hold at any size).  B = Q^T A sums m = 4.2M products in
+    FP32, whose rounding grows like sqrt(m) u32 (u32 = 2^-24) for a sum of
+    independent roundings; by Weyl's inequality |sigma_i - sigma_i(B exact)|
+    <= ||dB||_2, so the bound is 4 sqrt(m) u32 sigma_1 (4.9e-4 sigma_1)."""
+    import torch
+    m, n, k, s = 4_200_000, 64, 6, 10
+    announce(f"rsvd tall m={m} n={n} k={k}")
+    sig = 10.0 ** (-np.arange(k) / 2.0)
+    a = synth.torch_planted(m, n, sig, 9, "cuda")
+    u, sv, vt = rp().rsvd(a, k, s, 0, 3, "f16", "split_f16")
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    assert np.abs(host(sv) - sig).max() <= 4.0 * np.sqrt(m) * 2.0 ** -24 * sig[0]
+    ud = u.double()
+    gram = (ud.T @ ud).cpu().numpy()
+    assert np.abs(gram - np.eye(k)).max() < 1e-4
+    del a, u
+    torch.cuda.empty_cache()
