@@ -122,12 +122,12 @@ __host__ __device__ __forceinline__ int frag_slot(int g, int e) {
 // blocks (one row, four consecutive columns each), places the 8 values in
 // LDS at their fragment positions, and the workgroup then writes the 4 KiB
 // with one 16-byte store per thread.
-__global__ __launch_bounds__(256) void omega_packed_f16_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
-                                                               int64_t n, int64_t r, uint16_t* dst,
-                                                               int64_t kb_count, int64_t nt_count) {
+__device__ __forceinline__ void omega_packed_f16_block(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
+                                                       int64_t n, int64_t r, uint16_t* dst, int64_t nt_count,
+                                                       int64_t blk) {
     __shared__ uint16_t frag[4 * 64 * 8];
     const int64_t groups = nt_count / 4;                       // 4-tile groups per 32-row block
-    const int64_t kb = blockIdx.x / groups, ntg = blockIdx.x % groups;
+    const int64_t kb = blk / groups, ntg = blk % groups;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -150,6 +150,31 @@ __global__ __launch_bounds__(256) void omega_packed_f16_kernel(OmegaTables t, ui
     __syncthreads();
     const uint4 out = reinterpret_cast<const uint4*>(frag)[tid];
     reinterpret_cast<uint4*>(dst + (kb * nt_count + ntg * 4) * 64 * 8)[tid] = out;
+}
+
+__global__ __launch_bounds__(256) void omega_packed_f16_kernel(OmegaTables t, uint64_t seed, uint32_t stream_id,
+                                                               int64_t n, int64_t r, uint16_t* dst,
+                                                               int64_t kb_count, int64_t nt_count) {
+    (void)kb_count;
+    omega_packed_f16_block(t, seed, stream_id, n, r, dst, nt_count, blockIdx.x);
+}
+
+// Several problems' FP16 (or sparse) Omega in one launch: block b belongs to
+// the job g with jobs[g].start <= b < jobs[g + 1].start.
+__global__ __launch_bounds__(256) void omega_packed_f16_group_kernel(OmegaTables t,
+                                                                     const OmegaJob* __restrict__ jobs, int count) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const OmegaJob J = jobs[lo];
+    OmegaTables tj = t;
+    tj.sparse_t = J.sparse_t;
+    omega_packed_f16_block(tj, J.seed, J.stream_id, J.n, J.r, static_cast<uint16_t*>(J.dst), J.nt_count,
+                           b - J.start);
 }
 
 __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
@@ -403,6 +428,14 @@ hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     hipLaunchKernelGGL(omega_packed_f16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, seed, stream_id, n, r,
                        static_cast<uint16_t*>(dst.data), dst.kb_count, dst.nt_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega_packed_f16_group(const OmegaTables& t, const OmegaJob* jobs, int count, int64_t blocks,
+                                         hipStream_t s) {
+    if (count <= 0 || blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(omega_packed_f16_group_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t, jobs, count);
     return hipGetLastError();
 }
 

@@ -1945,6 +1945,10 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     // problem's Cholesky factor fits the one-workgroup kernel
     const bool grouped_stages = mp <= rpmi::kCholGroupMaxP;
     AuxImage im;
+    const bool omega_group = grouped_stages && algo == RP_ALGO_SPLIT_F16 &&
+                             (omega_type == RP_OMEGA_F16 || sparse_type(omega_type));
+    size_t om_jobs = 0;
+    int64_t om_blocks = 0;
     CholQr2Group cq_yq, cq_zw, cq_zw_m;
     TnGroup tn;
     FinishGroup fin;
@@ -1965,6 +1969,17 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         cq_zw_m = build_cholqr2_group(im, nrows, zs, wsp, ws, true, gpart);
         tn = build_tn_group(im, probs, ws, base + o_tnpart);
         fin = build_finish_group(im, probs, ws);
+        if (omega_group) {
+            // every problem's packed FP16 (or sparse) Omega in one launch
+            std::vector<rpmi::OmegaJob> oj(count);
+            for (int32_t g = 0; g < count; ++g) {
+                const rp_rsvd_problem& q = probs[g];
+                oj[g] = rpmi::OmegaJob{seed, (uint32_t)g, q.n, q.k + q.oversample, pk[g].data, pk[g].nt_count,
+                                       sparse_type(omega_type) ? sparse_threshold(omega_type, q.n) : 0, om_blocks};
+                om_blocks += pk[g].kb_count * (pk[g].nt_count / 4);
+            }
+            om_jobs = im.add(oj.data(), oj.size() * sizeof(rpmi::OmegaJob));
+        }
         if (im.bytes.size() > ctx->graph_aux_bytes) {
             if (ctx->graph_aux) RP_HIP(ctx, hipFree(ctx->graph_aux));
             ctx->graph_aux = nullptr;
@@ -1985,8 +2000,13 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
     }
     RP_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
     auto body = [&]() -> rp_status {
-        rp_status r2 = gen_omega(cs);
-        if (r2 != RP_OK) return r2;
+        rp_status r2 = RP_OK;
+        if (omega_group) {
+            RP_HIP(ctx, rpmi::launch_omega_packed_f16_group(tables(ctx), reinterpret_cast<const rpmi::OmegaJob*>(
+                                                                aux + om_jobs), count, om_blocks, cs));
+        } else if ((r2 = gen_omega(cs)) != RP_OK) {
+            return r2;
+        }
         if (!gp.entries.empty() && (r2 = launch_group_kernels(ctx, gp, ctx->graph_table, cs)) != RP_OK) return r2;
         for (int g : single) {
             const rp_rsvd_problem& q = probs[g];

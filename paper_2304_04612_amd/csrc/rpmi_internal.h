@@ -166,6 +166,20 @@ hipError_t launch_omega_e4m3(const OmegaTables& t, uint64_t seed, uint32_t strea
                              float* scale, hipStream_t s);
 hipError_t launch_omega_packed_f16(const OmegaTables& t, uint64_t seed, uint32_t stream_id,
                                    int64_t n, int64_t r, const PackedOmega& dst, hipStream_t s);
+// Several problems' packed FP16 (or sparse) Omega in one launch: job g owns
+// blocks [start, start + kb_count * nt_count / 4) (jobs sorted by start;
+// nt_count a multiple of 4), its own threshold sparse_t (0: Gaussian).
+struct OmegaJob {
+    uint64_t seed;
+    uint32_t stream_id;
+    int64_t n, r;
+    void* dst;
+    int64_t nt_count;
+    uint64_t sparse_t;
+    int64_t start;
+};
+hipError_t launch_omega_packed_f16_group(const OmegaTables& t, const OmegaJob* jobs, int count, int64_t blocks,
+                                         hipStream_t s);
 // Row-major Omega formats a caller can supply
 enum class OmegaSrc { F16, F32, E4M3 };
 // Reorder a caller (or generated) row-major Omega into fragment order.  For

@@ -113,6 +113,28 @@ def test_rsvd_batched_matches_oracle(omega_type):
         assert np.abs(host(sv) - 2.0 * first[j]).max() <= 1e-6 * 2.0 * first[j][0], j
 
 
+@pytest.mark.parametrize("kind", ["sparse3", "vsparse"])
+def test_rsvd_batched_sparse_omega_matches_oracle(kind):
+    """Batched RSVD with a sparse Omega_j (one grouped generation launch in
+    the graph): planted rank-k matrices plus N(0, 1e-6^2) noise (with Omega
+    in {-1, 0, 1} and FP16-valued split parts the projection's sums are
+    exact, so a noiseless rank-k A gives an exactly rank-k Y and a singular
+    CholeskyQR2 Gram); the singular values of the FP64 oracle's RSVD on the
+    same A and Omega_j."""
+    rng = np.random.default_rng(56)
+    batch = []
+    for (m, n, k, p) in synth.batched_problem_list(8, 57, 64, 600, 4, 20):
+        sig = 10.0 ** (-3.0 * np.arange(k) / (k - 1))
+        batch.append((synth.np_planted(m, n, sig, rng, noise_std=1e-6), k, p - k))
+    announce(f"rsvd_batched {kind} shapes {[a.shape for a, _, _ in batch]}")
+    outs = rp().rsvd_batched([dev(a) for a, _, _ in batch], [k for _, k, _ in batch], [s for _, _, s in batch], 0,
+                             19, kind)
+    assert rp().rp_get_device_status(clear=True) == rp().RP_OK
+    for j, ((a, k, s), (_, sv, _)) in enumerate(zip(batch, outs)):
+        _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), omega.omega_sparse(19, j, a.shape[1], k + s, kind), k, 0)
+        assert np.abs(host(sv) - sv_o).max() <= 1e-5 * sv_o[0], j
+
+
 def test_rsvd_batched_power_iteration_and_errors():
     batch = _planted_batch(4, 77, 80, 300, 5, 12)
     announce("rsvd_batched q=1")
