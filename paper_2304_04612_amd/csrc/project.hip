@@ -452,16 +452,33 @@ hipError_t launch_project_split_f16(const ProjArgs& a, hipStream_t s) {
                                   : launch_split_with<WideCfg, SplitTile>(a, s);
 }
 
-int64_t split_general_tile_m(int64_t r) { return r <= kNarrowMax ? SplitTile128::BM : SplitTile::BM; }
-int64_t split_general_tile_n(int64_t r) { return r <= kNarrowMax ? SplitTile128::BN : SplitTile::BN; }
+// general grouped tiles: 128 columns (r <= 128), 160 (r <= 160: the
+// batched problems' k + oversampling, 37.5% fewer products than a 256-column
+// tile), 256
+using SplitTile160 = Tile<2, 2, 2, 5, 2>;
+static_assert(SplitTile160::BN == 160 && SplitTile160::BM == SplitTile::BM && SplitTile128::BM == SplitTile::BM,
+              "one row tile for every width");
 
-hipError_t launch_project_split_f16_general_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                                    hipStream_t s) {
+int split_general_width_class(int64_t r) { return r <= kNarrowMax ? 0 : (r <= SplitTile160::BN ? 1 : 2); }
+int64_t split_general_tile_m(int64_t r) {
+    (void)r;
+    return SplitTile::BM;
+}
+int64_t split_general_tile_n(int64_t r) {
+    const int c = split_general_width_class(r);
+    return c == 0 ? SplitTile128::BN : (c == 1 ? SplitTile160::BN : SplitTile::BN);
+}
+
+hipError_t launch_project_split_f16_general_grouped(const GroupEntry* table, int count, int64_t blocks,
+                                                    int width_class, hipStream_t s) {
     if (count <= 0 || blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (narrow)
+    if (width_class == 0)
         hipLaunchKernelGGL((project_split_f16_general_grouped_kernel<SplitTile128, kSplitDepth>), dim3((unsigned)blocks),
                            dim3(SplitTile128::THREADS), 0, s, table, count);
+    else if (width_class == 1)
+        hipLaunchKernelGGL((project_split_f16_general_grouped_kernel<SplitTile160, kSplitDepth>), dim3((unsigned)blocks),
+                           dim3(SplitTile160::THREADS), 0, s, table, count);
     else
         hipLaunchKernelGGL((project_split_f16_general_grouped_kernel<SplitTile, kSplitDepth>), dim3((unsigned)blocks),
                            dim3(SplitTile::THREADS), 0, s, table, count);

@@ -719,7 +719,8 @@ rp_status ensure_table(rp_ctx ctx, size_t entries) {
 // `cu_scale`) and its split-K counters and partials laid out in the context
 // buffers; the others go to the general kernel, one launch per column width,
 // longest contraction first (each of its tiles runs the whole contraction).
-// Table order: fast narrow, fast wide, general narrow, general wide.
+// Table order: fast narrow, fast wide, then the general kernel's three
+// column widths (128, 160, 256).
 struct GroupPlan {
     struct Seg {
         int first = 0, count = 0;
@@ -727,7 +728,7 @@ struct GroupPlan {
         int64_t rblocks = 0;   // reduction-pass blocks (LDS-staged launches)
     };
     std::vector<rpmi::GroupEntry> entries;
-    Seg seg[4];   // fast narrow, fast wide, general narrow, general wide
+    Seg seg[5];   // fast narrow, fast wide, general r <= 128, r <= 160, r > 160
     bool narrow_lds = false;   // fast narrow problems on the LDS-staged kernel
 };
 
@@ -764,14 +765,14 @@ rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, doubl
     char* pbase = static_cast<char*>(ctx->split_ws);
     out->entries.clear();
     out->narrow_lds = narrow_lds;
-    for (int sg = 0; sg < 4; ++sg) {
-        const bool gen = sg >= 2, narrow = (sg & 1) == 0;
+    for (int sg = 0; sg < 5; ++sg) {
+        const bool gen = sg >= 2, narrow = sg == 0;
         GroupPlan::Seg& seg = out->seg[sg];
         seg.first = (int)out->entries.size();
         int64_t start = 0, rstart = 0;
         const bool lds = sg == 1 || (sg == 0 && narrow_lds);
         for (int g : gen ? general : fast) {
-            if ((probs[g].r <= 128) != narrow) continue;
+            if (gen ? rpmi::split_general_width_class(probs[g].r) != sg - 2 : (probs[g].r <= 128) != narrow) continue;
             rpmi::GroupEntry e;
             e.p = probs[g];
             int64_t bm, bn;
@@ -808,7 +809,7 @@ rp_status plan_group(rp_ctx ctx, const std::vector<rpmi::ProjArgs>& probs, doubl
 
 // Launch a planned group whose table is already on the device.
 rp_status launch_group_kernels(rp_ctx ctx, const GroupPlan& gp, const rpmi::GroupEntry* table, hipStream_t s) {
-    for (int sg = 0; sg < 4; ++sg) {
+    for (int sg = 0; sg < 5; ++sg) {
         const GroupPlan::Seg& seg = gp.seg[sg];
         if (seg.count == 0) continue;
         if (sg == 0 && gp.narrow_lds)
@@ -818,7 +819,7 @@ rp_status launch_group_kernels(rp_ctx ctx, const GroupPlan& gp, const rpmi::Grou
                                                                nullptr, seg.rblocks));
         else
             RP_HIP(ctx, rpmi::launch_project_split_f16_general_grouped(table + seg.first, seg.count, seg.blocks,
-                                                                       sg == 2, s));
+                                                                       sg - 2, s));
     }
     return RP_OK;
 }

@@ -111,11 +111,13 @@ hipError_t launch_split_group_narrow(const GroupEntry* table, int count, int64_t
 bool split_fast_ok(const ProjArgs& a);
 // Projections of any layout (element loads, two accumulators, no contraction
 // split; entries' fold_flags must be null) in one table-driven launch per
-// column width (narrow: r <= 128); tiles from split_general_tile_m/_n.
+// column width class (0: r <= 128, 1: r <= 160, 2: wider); tiles from
+// split_general_tile_m/_n.
+int split_general_width_class(int64_t r);
 int64_t split_general_tile_m(int64_t r);
 int64_t split_general_tile_n(int64_t r);
-hipError_t launch_project_split_f16_general_grouped(const GroupEntry* table, int count, int64_t blocks, bool narrow,
-                                                    hipStream_t s);
+hipError_t launch_project_split_f16_general_grouped(const GroupEntry* table, int count, int64_t blocks,
+                                                    int width_class, hipStream_t s);
 
 // Workspace the split-FP16 projection needs for (m, r) (0 if none) and the
 // contraction split it will use; the counters must be zero initially.
