@@ -163,14 +163,14 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_group_kernel(const Chol
 }
 
 // C (N x P) = A^T Q for A (K x N, lda) and Q (K x P, ldq) on
-// v_mfma_f32_16x16x4f32: a wave owns 64 x 64 of C as 4 x 4 MFMA tiles whose
-// rows and columns are permuted to suit the loads.  VEC (lda, ldq, ldc
-// multiples of 4, 16-byte aligned bases): lane c reads four consecutive
-// elements of a row of A and of Q with one 16-byte load (tile a, MFMA row c
-// is C row i0 + 4c + a).  Otherwise lane c reads column i0 + 16a + c, so the
-// 16 lanes of a row read 64 consecutive bytes with each 4-byte load (MFMA row
-// c of tile a is C row i0 + 16a + c).
-template <bool VEC>
+// v_mfma_f32_16x16x4f32: a wave owns 64 x 64 of C as 4 x 4 MFMA tiles; lane c
+// reads column i0 + 16a + c of a row of A (and j0 + 16b + c of a row of Q), so
+// the 16 lanes of a row read 64 consecutive bytes with each 4-byte load,
+// whatever the alignment of lda, ldq and the bases.  The four waves of a
+// workgroup take the job's wp 64-column tiles of P first (wp = min(tiles of P,
+// 4)) and 4 / wp column blocks of A second, so that the waves sharing a block
+// of A run on one compute unit and A leaves HBM once for all of P.  The next
+// 16 rows are loaded before the products of the current ones.
 __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
                                                                 const int64_t* __restrict__ starts, int count) {
     typedef float f4 __attribute__((ext_vector_type(4)));
@@ -181,40 +181,41 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
     const int kz = (int)(local / per_k);
     const int64_t rest = local - kz * per_k;
     const int64_t bx = rest % J.tiles_x, by = rest / J.tiles_x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wp = J.wp, wn = 4 / wp;
+    if (wave >= wp * wn) return;              // wp = 3: the fourth wave has no tile (no barrier follows)
+    const int64_t i0 = (by * wn + wave / wp) * 64, j0 = (bx * wp + wave % wp) * 64;
+    if (i0 >= J.N || j0 >= J.P) return;
     const int64_t kbeg = kz * J.kchunk, kend = J.K < kbeg + J.kchunk ? J.K : kbeg + J.kchunk;
     float* const Cout = J.ksplit > 1 ? J.part + kz * J.N * J.P : J.C;
     const int64_t ldc = J.ksplit > 1 ? J.P : J.ldc;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t i0 = (by * 4 + wave) * 64, j0 = bx * 64;
-    const int64_t ia = i0 + 4 * c, jq = j0 + 4 * c;
-    const bool a_full = ia + 3 < J.N, q_full = jq + 3 < J.P;
     f4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    auto load4 = [&](const float* row, int64_t base, int64_t lim, bool full) -> f4 {
+    auto load4 = [&](const float* row, int64_t base, int64_t lim) -> f4 {
         f4 v;
-        if constexpr (VEC) {
-            if (full) return *reinterpret_cast<const f4*>(row + base + 4 * c);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = base + 4 * c + e < lim ? row[base + 4 * c + e] : 0.0f;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = base + 16 * e + c < lim ? row[base + 16 * e + c] : 0.0f;
-        }
+        for (int e = 0; e < 4; ++e) v[e] = base + 16 * e + c < lim ? row[base + 16 * e + c] : 0.0f;
         return v;
     };
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-        f4 av[4], qv[4];
+    auto load_step = [&](int64_t k0, f4* av, f4* qv) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t k = k0 + 4 * u + g;
             const bool in = k < kend;
-            av[u] = in ? load4(J.A + k * J.lda, i0, J.N, a_full) : f4{0.f, 0.f, 0.f, 0.f};
-            qv[u] = in ? load4(J.Q + k * J.ldq, j0, J.P, q_full) : f4{0.f, 0.f, 0.f, 0.f};
+            av[u] = in ? load4(J.A + k * J.lda, i0, J.N) : f4{0.f, 0.f, 0.f, 0.f};
+            qv[u] = in ? load4(J.Q + k * J.ldq, j0, J.P) : f4{0.f, 0.f, 0.f, 0.f};
         }
+    };
+    f4 av[4], qv[4];
+    load_step(kbeg, av, qv);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+        f4 an[4], qn[4];
+        const bool more = k0 + 16 < kend;
+        if (more) load_step(k0 + 16, an, qn);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -222,37 +223,26 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u] = an[u];
+                qv[u] = qn[u];
+            }
+        }
     }
     // lane (c, g) holds D[4g + e][c] of every MFMA tile
-    if constexpr (VEC) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t i = i0 + 4 * (4 * g + e) + a;
-                if (i >= J.N) continue;
-                float* crow = Cout + i * ldc;
-                if (q_full) {
-                    *reinterpret_cast<f4*>(crow + jq) = f4{acc[a][0][e], acc[a][1][e], acc[a][2][e], acc[a][3][e]};
-                } else {
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + 16 * a + 4 * g + e;
+            if (i >= J.N) continue;
+            float* crow = Cout + i * ldc;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (jq + b < J.P) crow[jq + b] = acc[a][b][e];
-                }
-            }
-    } else {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t i = i0 + 16 * a + 4 * g + e;
-                if (i >= J.N) continue;
-                float* crow = Cout + i * ldc;
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (j0 + 16 * b + c < J.P) crow[j0 + 16 * b + c] = acc[a][b][e];
-            }
-    }
+            for (int b = 0; b < 4; ++b)
+                if (j0 + 16 * b + c < J.P) crow[j0 + 16 * b + c] = acc[a][b][e];
+        }
 }
 
 // sigma_j = |w_j| (column norms of W, row-major n x n); rank by sigma
@@ -363,8 +353,12 @@ hipError_t chol_inv_group(const CholJob* jobs, int count, int max_p, unsigned in
     return hipGetLastError();
 }
 
-int64_t tn_group_tiles_x(int64_t P) { return (P + 63) / 64; }
-int64_t tn_group_tiles(int64_t N, int64_t P) { return ((P + 63) / 64) * ((N + 255) / 256); }
+void tn_group_shape(TnJob& j) {
+    const int64_t tp = (j.P + 63) / 64;
+    j.wp = tp < 4 ? (int)(tp < 1 ? 1 : tp) : 4;
+    j.tiles_x = (tp + j.wp - 1) / j.wp;
+    j.tiles_y = (j.N + 64 * (4 / j.wp) - 1) / (64 * (4 / j.wp));
+}
 
 // C = sum of the job's partials, in order (kSumBlocks workgroups per job)
 __global__ __launch_bounds__(256) void tn_sum_group_kernel(const TnJob* __restrict__ jobs) {
@@ -379,16 +373,11 @@ __global__ __launch_bounds__(256) void tn_sum_group_kernel(const TnJob* __restri
     }
 }
 
-hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
-                             bool any_split, hipStream_t s) {
+hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool any_split,
+                             hipStream_t s) {
     if (count <= 0 || blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    if (vec)
-        hipLaunchKernelGGL(gemm_tn_f32_group_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
-                           count);
-    else
-        hipLaunchKernelGGL(gemm_tn_f32_group_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts,
-                           count);
+    hipLaunchKernelGGL(gemm_tn_f32_group_kernel, dim3((unsigned)blocks), dim3(256), 0, s, jobs, starts, count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !any_split) return e;
     hipLaunchKernelGGL(tn_sum_group_kernel, dim3((unsigned)count, kSumBlocks), dim3(256), 0, s, jobs);

@@ -1509,19 +1509,26 @@ rp_status run_cholqr2_group(rp_ctx ctx, const CholQr2Group& G, char* aux, hipStr
     return RP_OK;
 }
 
-// Z_g = A_g^T Q_g for every problem, as two grouped launches: the jobs on the
-// 16-byte path and the others.
+// Z_g = A_g^T Q_g for every problem, as one grouped launch (plus the in-order
+// sum of the contraction chunks where a problem is split).
 struct TnGroup {
-    size_t jobs[2] = {0, 0}, starts[2] = {0, 0};
-    int count[2] = {0, 0};
-    int64_t blocks[2] = {0, 0};
-    bool any_split[2] = {false, false};
+    size_t jobs = 0, starts = 0;
+    int count = 0;
+    int64_t blocks = 0;
+    bool any_split = false;
 };
+
+int64_t tn_tiles(int64_t N, int64_t P) {
+    rpmi::TnJob j{};
+    j.N = N; j.P = P;
+    rpmi::tn_group_shape(j);
+    return j.tiles_x * j.tiles_y;
+}
 
 // Contraction split of a grouped A^T Q with few output tiles: enough chunks
 // (of at least 1024 rows, at most 8) to give the problem about 24 workgroups.
 int tn_split(int64_t K, int64_t N, int64_t P) {
-    const int64_t tiles = rpmi::tn_group_tiles(N, P);
+    const int64_t tiles = tn_tiles(N, P);
     int64_t s = (24 + tiles - 1) / tiles;
     const int64_t kmax = K / 1024;
     s = s > kmax ? kmax : s;
@@ -1541,8 +1548,8 @@ size_t tn_part_bytes(const rp_rsvd_problem* probs, int32_t count) {
 
 TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::vector<RsvdScratch>& ws, char* part) {
     TnGroup T;
-    std::vector<rpmi::TnJob> jobs[2];
-    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    std::vector<rpmi::TnJob> jobs;
+    std::vector<int64_t> starts;
     for (size_t i = 0; i < ws.size(); ++i) {
         const rp_rsvd_problem& q = probs[i];
         const RsvdScratch& w = ws[i];
@@ -1557,37 +1564,27 @@ TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::ve
         if (j.ksplit > 1) {
             j.part = reinterpret_cast<float*>(part);
             part += ((size_t)sp * q.n * w.p * sizeof(float) + 255) & ~size_t(255);
+            T.any_split = true;
         }
-        const bool vec = q.lda % 4 == 0 && w.p % 4 == 0 && al(q.A) && al(w.Q) && al(w.Z);
-        jobs[vec ? 1 : 0].push_back(j);
+        rpmi::tn_group_shape(j);
+        j.start = T.blocks;
+        starts.push_back(T.blocks);
+        T.blocks += j.tiles_x * j.tiles_y * j.ksplit;
+        jobs.push_back(j);
     }
-    for (int v = 0; v < 2; ++v) {
-        std::vector<int64_t> starts(jobs[v].size());
-        int64_t b = 0;
-        for (size_t i = 0; i < jobs[v].size(); ++i) {
-            jobs[v][i].tiles_x = rpmi::tn_group_tiles_x(jobs[v][i].P);
-            jobs[v][i].tiles_y = (jobs[v][i].N + 255) / 256;
-            jobs[v][i].start = b;
-            starts[i] = b;
-            b += rpmi::tn_group_tiles(jobs[v][i].N, jobs[v][i].P) * jobs[v][i].ksplit;
-            if (jobs[v][i].ksplit > 1) T.any_split[v] = true;
-        }
-        T.count[v] = (int)jobs[v].size();
-        T.blocks[v] = b;
-        if (!jobs[v].empty()) {
-            T.jobs[v] = im.add(jobs[v].data(), jobs[v].size() * sizeof(rpmi::TnJob));
-            T.starts[v] = im.add(starts.data(), starts.size() * sizeof(int64_t));
-        }
+    T.count = (int)jobs.size();
+    if (!jobs.empty()) {
+        T.jobs = im.add(jobs.data(), jobs.size() * sizeof(rpmi::TnJob));
+        T.starts = im.add(starts.data(), starts.size() * sizeof(int64_t));
     }
     return T;
 }
 
 rp_status run_tn_group(rp_ctx ctx, const TnGroup& T, char* aux, hipStream_t s) {
-    for (int v = 0; v < 2; ++v)
-        if (T.count[v] > 0)
-            RP_HIP(ctx, rpmi::gemm_tn_f32_group(reinterpret_cast<const rpmi::TnJob*>(aux + T.jobs[v]),
-                                                reinterpret_cast<const int64_t*>(aux + T.starts[v]), T.count[v],
-                                                T.blocks[v], v == 1, T.any_split[v], s));
+    if (T.count > 0)
+        RP_HIP(ctx, rpmi::gemm_tn_f32_group(reinterpret_cast<const rpmi::TnJob*>(aux + T.jobs),
+                                            reinterpret_cast<const int64_t*>(aux + T.starts), T.count, T.blocks,
+                                            T.any_split, s));
     return RP_OK;
 }
 

@@ -362,15 +362,15 @@ struct TnJob {                        // C (N x P) = A^T Q, A K x N, Q K x P, al
     int64_t ldq;
     float* C;
     int64_t ldc;
-    int64_t tiles_x, tiles_y, start;
+    int64_t tiles_x, tiles_y, start;  // workgroups along P and along N (tn_group_shape)
+    int wp;                           // 64-column tiles of P per workgroup (1 .. 4)
     int64_t kchunk;                   // rows of A per contraction chunk
     int ksplit;                       // > 1: chunk kz writes part + kz N P (ld P); C = their sum, in order
     float* part;
 };
-int64_t tn_group_tiles_x(int64_t P);
-int64_t tn_group_tiles(int64_t N, int64_t P);
-// vec: every job has 16-byte aligned A, Q, C and lda, ldq, ldc multiples of 4
-hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks, bool vec,
+// sets wp, tiles_x and tiles_y from N and P
+void tn_group_shape(TnJob& j);
+hipError_t gemm_tn_f32_group(const TnJob* jobs, const int64_t* starts, int count, int64_t blocks,
                              bool any_split, hipStream_t s);
 
 struct SvdJob {                       // after the Jacobi iteration on W (n x n) with V
