@@ -170,7 +170,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_group_kernel(const Chol
 // workgroup take the job's wp 64-column tiles of P first (wp = min(tiles of P,
 // 4)) and 4 / wp column blocks of A second, so that the waves sharing a block
 // of A run on one compute unit and A leaves HBM once for all of P.  The next
-// 16 rows are loaded before the products of the current ones.
+// 16 rows are loaded before the products of the current ones.  Jobs come
+// longest contraction chunk first (the host orders the table), so that the
+// longest waves start first.
 __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
                                                                 const int64_t* __restrict__ starts, int count) {
     typedef float f4 __attribute__((ext_vector_type(4)));

@@ -1567,10 +1567,16 @@ TnGroup build_tn_group(AuxImage& im, const rp_rsvd_problem* probs, const std::ve
             T.any_split = true;
         }
         rpmi::tn_group_shape(j);
+        jobs.push_back(j);
+    }
+    // every wave of a job runs kchunk rows: longest first (a stable order, so
+    // the table is the same on every call)
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [](const rpmi::TnJob& x, const rpmi::TnJob& y) { return x.kchunk > y.kchunk; });
+    for (rpmi::TnJob& j : jobs) {
         j.start = T.blocks;
         starts.push_back(T.blocks);
         T.blocks += j.tiles_x * j.tiles_y * j.ksplit;
-        jobs.push_back(j);
     }
     T.count = (int)jobs.size();
     if (!jobs.empty()) {
