@@ -399,10 +399,17 @@ typedef struct {
  * problem-shape signature (the grouped projection is timed at a few
  * compute-unit shares; the fastest is kept in the context).  The whole
  * sequence (Omega generation, projections, every problem's CholeskyQR2,
- * B, SVD and U, V^T stages) is captured in a HIP graph on a context stream
- * and launched on `stream`; a later call with the same problems, buffers and
- * options replays the graph, which reads A afresh.  The first call of a
- * problem set synchronises the device.  Outputs per problem as in rsvd.
+ * B, SVD and U, V^T stages) is captured in two HIP graphs on a context
+ * stream and launched on `stream`; a later call with the same problems,
+ * buffers and options replays them, reading A afresh.  The first graph ends
+ * after the first 10 sweeps of the grouped Jacobi SVD (RPMI_BATCHED_GRAPH_SWEEPS
+ * = an integer in [0, 1000] in the environment at rp_create sets another
+ * count); the host then reads the number of problems not yet converged
+ * (synchronising `stream`) and, while some are open and the sweep bound of
+ * rsvd allows, issues one more sweep and reads it again; the second graph
+ * holds the Jacobi final step and the U, V^T products.  Every call
+ * therefore synchronises `stream` once; the first call of a problem set
+ * synchronises the device.  Outputs per problem as in rsvd.
  */
 rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, int32_t power_iters,
                        uint64_t seed, rp_omega_t omega_type, void* stream);

@@ -847,26 +847,36 @@ hipError_t gemm_tn_f32(int64_t N, int64_t P, int64_t K, const float* A, int64_t 
     return hipSuccess;
 }
 
-hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n,
-                            int max_sweeps, double tol, unsigned int* status, hipStream_t s, const int* poll_flag) {
+// Rounds take the block form once a problem has more than one block pair.
+// Its rotations come from the block's Gram, whose rounding keeps the last
+// off-diagonal ratios near 1e-13 for a while (16 sweeps instead of 14 on a
+// 640 x 640 R_B^T with sigma in [0.018, 1] at 1e-12), so it stops at 1e-12
+// (singular values then agree to far below FP32 rounding) and may take up to
+// 8 more sweeps.
+static bool jacobi_block_form(int max_n) { return max_n > 2 * kJacobiBlock; }
+
+int jacobi_group_sweep_bound(int max_n, int max_sweeps) {
+    return jacobi_block_form(max_n) ? max_sweeps + 8 : max_sweeps;
+}
+
+hipError_t jacobi_group_prep(const JacobiProb* tab, int count, int max_n, hipStream_t s) {
     if (count <= 0 || max_n <= 0) return hipSuccess;
     if (max_n > 1024) return hipErrorInvalidValue;    // the round kernels hold n <= 1024 elements in registers
-    hipError_t e;
     const int gx = grid1d((int64_t)max_n * max_n) < 1024 ? grid1d((int64_t)max_n * max_n) : 1024;
     hipLaunchKernelGGL(jacobi_prep_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // the block form once a problem has more than one block pair per round.
-    // Its rotations come from the block's Gram, whose rounding keeps the
-    // last off-diagonal ratios near 1e-13 for a while (16 sweeps instead of
-    // 14 on a 640 x 640 R_B^T with sigma in [0.018, 1] at 1e-12), so it stops
-    // at 1e-12 (singular values then agree to far below FP32 rounding) and
-    // may take up to 8 more sweeps.
-    const bool block = max_n > 2 * kJacobiBlock;
+    return hipGetLastError();
+}
+
+hipError_t jacobi_group_sweeps(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n,
+                               int sweep_begin, int sweep_end, double tol, hipStream_t s, const int* poll_flag) {
+    if (count <= 0 || max_n <= 0) return hipSuccess;
+    if (max_n > 1024) return hipErrorInvalidValue;
+    hipError_t e;
+    const bool block = jacobi_block_form(max_n);
     const int max_nb = (max_n + kJacobiBlock - 1) / kJacobiBlock;
     const int max_m = block ? max_nb + (max_nb & 1) : max_n + (max_n & 1);
     const double btol = tol > 1e-12 ? tol : 1e-12;
-    if (block) max_sweeps += 8;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int sweep = sweep_begin; sweep < sweep_end; ++sweep) {
         for (int round = 0; round < max_m - 1; ++round) {
             if (block && max_n <= 256)
                 hipLaunchKernelGGL(jacobi_block_round_kernel<1>, dim3((unsigned)total_bpairs), dim3(256), 0, s, tab,
@@ -895,8 +905,44 @@ hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, i
             if (done) break;
         }
     }
+    return hipSuccess;
+}
+
+// *out = the number of problems whose converged flag is not set (one workgroup)
+__global__ __launch_bounds__(256) void jacobi_open_kernel(const JacobiProb* tab, int count, int* out) {
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int g = threadIdx.x; g < count; g += blockDim.x) mine += tab[g].flags[0] ? 0 : 1;
+    if (mine) atomicAdd(&total, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = total;
+}
+
+hipError_t jacobi_group_open(const JacobiProb* tab, int count, int* out, hipStream_t s) {
+    hipLaunchKernelGGL(jacobi_open_kernel, dim3(1), dim3(256), 0, s, tab, count, out);
+    return hipGetLastError();
+}
+
+hipError_t jacobi_group_final(const JacobiProb* tab, int count, int max_n, unsigned int* status, hipStream_t s) {
+    if (count <= 0 || max_n <= 0) return hipSuccess;
+    if (max_n > 1024) return hipErrorInvalidValue;
+    const int gx = grid1d((int64_t)max_n * max_n) < 1024 ? grid1d((int64_t)max_n * max_n) : 1024;
     hipLaunchKernelGGL(jacobi_final_kernel, dim3((unsigned)gx, (unsigned)count), dim3(256), 0, s, tab, status);
     return hipGetLastError();
+}
+
+hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n,
+                            int max_sweeps, double tol, unsigned int* status, hipStream_t s, const int* poll_flag) {
+    if (count <= 0 || max_n <= 0) return hipSuccess;
+    if (max_n > 1024) return hipErrorInvalidValue;
+    hipError_t e;
+    if ((e = jacobi_group_prep(tab, count, max_n, s)) != hipSuccess) return e;
+    if ((e = jacobi_group_sweeps(tab, count, total_pairs, total_bpairs, max_n, 0,
+                                 jacobi_group_sweep_bound(max_n, max_sweeps), tol, s, poll_flag)) != hipSuccess)
+        return e;
+    return jacobi_group_final(tab, count, max_n, status, s);
 }
 
 hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStream_t s) {

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -45,8 +46,15 @@ struct rp_ctx_s {
     // the set, its buffers and the context buffers are unchanged), its own
     // device table of grouped projections, and the autotuner's choices
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraphExec_t graph_exec = nullptr;      // Omega .. the first graph_jac.graph_sweeps Jacobi sweeps
+    hipGraphExec_t graph_exec2 = nullptr;     // the Jacobi final step and the finishing products
     uint64_t graph_key = 0;
+    // the batched Jacobi between the two graphs: sweeps beyond the captured
+    // ones run eagerly while a problem is open (d_jopen: open problems)
+    struct {
+        int count, pairs, bpairs, max_n, graph_sweeps, bound;
+    } graph_jac = {0, 0, 0, 0, 0, 0};
+    int* d_jopen = nullptr;
     rpmi::GroupEntry* graph_table = nullptr;
     size_t graph_table_entries = 0;
     rpmi::JacobiProb* graph_jtab = nullptr;   // the batched Jacobi table read by the graph
@@ -63,6 +71,7 @@ struct rp_ctx_s {
     std::unordered_map<uint64_t, TuneEntry> tuned_scale;
     std::string tuning_file;              // RPMI_TUNING_FILE at creation ("" if unset)
     int force_form = -1;                  // RPMI_GROUP_FORM at creation (0 or 1), else -1
+    int graph_sweeps = -1;                // RPMI_BATCHED_GRAPH_SWEEPS at creation (>= 0), else -1: the default
     // generated Omega kept in device memory, keyed by what defines its bits
     // (seed, stream_id, n, r, type) and by the fragment format (algorithm);
     // least recently used entries are freed beyond kOmegaCacheBytes
@@ -287,6 +296,11 @@ rp_status rp_create(rp_ctx* out, int device) {
             return cleanup(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
         ctx->noalloc_scratch = static_cast<unsigned char*>(p);
     }
+    if (const char* gs = getenv("RPMI_BATCHED_GRAPH_SWEEPS")) {
+        char* end = nullptr;
+        const long v = strtol(gs, &end, 10);
+        if (end != gs && *end == '\0' && v >= 0 && v <= 1000) ctx->graph_sweeps = (int)v;
+    }
     if (const char* ff = getenv("RPMI_GROUP_FORM")) {
         if (ff[0] == '0' && ff[1] == '\0') ctx->force_form = 0;
         if (ff[0] == '1' && ff[1] == '\0') ctx->force_form = 1;
@@ -333,6 +347,8 @@ rp_status rp_destroy(rp_ctx ctx) {
     if (ctx->table) (void)hipFree(ctx->table);
     if (ctx->fold_flags) (void)hipFree(ctx->fold_flags);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph_exec2) (void)hipGraphExecDestroy(ctx->graph_exec2);
+    if (ctx->d_jopen) (void)hipFree(ctx->d_jopen);
     if (ctx->graph_table) (void)hipFree(ctx->graph_table);
     if (ctx->graph_jtab) (void)hipFree(ctx->graph_jtab);
     if (ctx->graph_aux) (void)hipFree(ctx->graph_aux);
@@ -1183,6 +1199,11 @@ struct RsvdScratch {
 
 constexpr int kJacobiSweeps = 16;
 constexpr double kJacobiTol = 1e-14;
+// Jacobi sweeps recorded in the batched call's first graph; the batched
+// problems have converged within them (9 sweeps on 256 problems of width 26
+// to 160), and any further sweep up to the bound runs eagerly, only while a
+// problem is open
+constexpr int kBatchedGraphSweeps = 10;
 
 rp_status rsvd_check(rp_ctx ctx, const rp_rsvd_problem& q, int32_t power_iters) {
     const int64_t p = q.k + q.oversample;
@@ -1794,6 +1815,27 @@ rp_status rp_project_grouped(rp_ctx ctx, int32_t count, const rp_project_problem
     return launch_group(ctx, gp, ctx->table, s);
 }
 
+// One batched call from its two graphs: the first (through the first Jacobi
+// sweeps), then while some problem is open and the sweep bound allows, one
+// eager sweep at a time (the host reads the open count after each: a stream
+// synchronisation), then the second graph.
+rp_status run_batched_graphs(rp_ctx ctx, hipStream_t s) {
+    const auto& J = ctx->graph_jac;
+    RP_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
+    const rpmi::JacobiProb* jtab = ctx->graph_jtab;
+    for (int sweep = J.graph_sweeps; sweep < J.bound; ++sweep) {
+        int open = 0;
+        RP_HIP(ctx, rpmi::jacobi_group_open(jtab, J.count, ctx->d_jopen, s));
+        RP_HIP(ctx, hipMemcpyAsync(&open, ctx->d_jopen, sizeof open, hipMemcpyDeviceToHost, s));
+        RP_HIP(ctx, hipStreamSynchronize(s));
+        if (open == 0) break;
+        RP_HIP(ctx, rpmi::jacobi_group_sweeps(jtab, J.count, J.pairs, J.bpairs, J.max_n, sweep, sweep + 1,
+                                              kJacobiTol, s));
+    }
+    RP_HIP(ctx, hipGraphLaunch(ctx->graph_exec2, s));
+    return RP_OK;
+}
+
 rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, int32_t power_iters,
                        uint64_t seed, rp_omega_t omega_type, void* stream) {
     if (!ctx) return fail(nullptr, RP_ERR_INVALID_ARG, "ctx is NULL");
@@ -1884,10 +1926,7 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         key = mix(mix(key, (uint64_t)(uintptr_t)ctx->split_ws), (uint64_t)ctx->split_ws_bytes);
         return mix(mix(key, (uint64_t)(uintptr_t)ctx->split_counters), (uint64_t)ctx->split_counter_bytes);
     };
-    if (ctx->graph_exec && call_key() == ctx->graph_key) {
-        RP_HIP(ctx, hipGraphLaunch(ctx->graph_exec, s));
-        return RP_OK;
-    }
+    if (ctx->graph_exec && ctx->graph_exec2 && call_key() == ctx->graph_key) return run_batched_graphs(ctx, s);
 
     auto gen_omega = [&](hipStream_t st_) -> rp_status {
         for (int32_t g = 0; g < count; ++g) {
@@ -2002,7 +2041,14 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
         (void)hipGraphExecDestroy(ctx->graph_exec);
         ctx->graph_exec = nullptr;
     }
-    RP_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (ctx->graph_exec2) {
+        (void)hipGraphExecDestroy(ctx->graph_exec2);
+        ctx->graph_exec2 = nullptr;
+    }
+    if (!ctx->d_jopen) RP_HIP(ctx, hipMalloc(&ctx->d_jopen, sizeof(int)));
+    const int jbound = rpmi::jacobi_group_sweep_bound((int)mp, kJacobiSweeps);
+    const int jwant = ctx->graph_sweeps >= 0 ? ctx->graph_sweeps : kBatchedGraphSweeps;
+    const int jgraph = jbound < jwant ? jbound : jwant;
     auto body = [&]() -> rp_status {
         rp_status r2 = RP_OK;
         if (omega_group) {
@@ -2050,30 +2096,45 @@ rp_status rsvd_batched(rp_ctx ctx, int32_t count, const rp_rsvd_problem* probs, 
                 if (r2 != RP_OK) return r2;
             }
         }
-        // one parallel Jacobi SVD over every problem's R_B^T
-        RP_HIP(ctx, rpmi::jacobi_svd_group(jtab, count, jpairs, jbpairs, (int)mp, kJacobiSweeps, kJacobiTol,
-                                           ctx->d_status, cs));
+        // one parallel Jacobi SVD over every problem's R_B^T: its first sweeps
+        RP_HIP(ctx, rpmi::jacobi_group_prep(jtab, count, (int)mp, cs));
+        RP_HIP(ctx, rpmi::jacobi_group_sweeps(jtab, count, jpairs, jbpairs, (int)mp, 0, jgraph, kJacobiTol, cs));
+        return RP_OK;
+    };
+    // the second graph: the Jacobi final step and Algorithm 1 line 5
+    auto body2 = [&]() -> rp_status {
+        rp_status r2 = RP_OK;
+        RP_HIP(ctx, rpmi::jacobi_group_final(jtab, count, (int)mp, ctx->d_status, cs));
         if (grouped_stages) return run_finish_group(ctx, fin, aux, cs);
         for (int32_t g = 0; g < count; ++g)
             if ((r2 = rsvd_after_svd(ctx, probs[g], probs[g].k + probs[g].oversample, ws[g], cs)) != RP_OK) return r2;
         return RP_OK;
     };
-    const rp_status body_st = body();
-    hipGraph_t graph = nullptr;
-    const hipError_t ce = hipStreamEndCapture(cs, &graph);
-    if (body_st != RP_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return body_st;
+    auto capture = [&](const std::function<rp_status()>& fn, hipGraphExec_t* out) -> rp_status {
+        RP_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        const rp_status body_st = fn();
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (body_st != RP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return body_st;
+        }
+        if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
+        const hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return hip_fail(ctx, ie, "hipGraphInstantiate");
+        return RP_OK;
+    };
+    rp_status cst = capture(body, &ctx->graph_exec);
+    if (cst == RP_OK) cst = capture(body2, &ctx->graph_exec2);
+    if (cst != RP_OK) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+        return cst;
     }
-    if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamEndCapture");
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) return hip_fail(ctx, ie, "hipGraphInstantiate");
-    ctx->graph_exec = exec;
+    ctx->graph_jac = {count, jpairs, jbpairs, (int)mp, jgraph, jbound};
     ctx->graph_key = call_key();
-    RP_HIP(ctx, hipGraphLaunch(exec, s));
-    return RP_OK;
+    return run_batched_graphs(ctx, s);
 }
 
 }  // extern "C"

@@ -302,6 +302,18 @@ hipError_t launch_set_jacobi_prob(JacobiProb* dst, const JacobiProb& v, hipStrea
 // every sweep, synchronising the stream, and stops issuing sweeps once set.
 hipError_t jacobi_svd_group(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n, int max_sweeps,
                             double tol, unsigned int* status, hipStream_t s, const int* poll_flag = nullptr);
+// The phases of jacobi_svd_group, for a caller that runs the sweeps in parts:
+// prep (W to column-major, V = I, flags cleared), sweeps [sweep_begin,
+// sweep_end), final (W, V back to row-major; not-converged status).  The
+// sweep bound is max_sweeps plus the block form's 8.  jacobi_group_open
+// writes the number of problems not yet converged to *out (device int).
+int jacobi_group_sweep_bound(int max_n, int max_sweeps);
+hipError_t jacobi_group_prep(const JacobiProb* tab, int count, int max_n, hipStream_t s);
+hipError_t jacobi_group_sweeps(const JacobiProb* tab, int count, int total_pairs, int total_bpairs, int max_n,
+                               int sweep_begin, int sweep_end, double tol, hipStream_t s,
+                               const int* poll_flag = nullptr);
+hipError_t jacobi_group_open(const JacobiProb* tab, int count, int* out, hipStream_t s);
+hipError_t jacobi_group_final(const JacobiProb* tab, int count, int max_n, unsigned int* status, hipStream_t s);
 hipError_t svd_finish(const double* W, const double* V, int n, int ncols, double* sig, int* order, double* Ur,
                       double* Vr, hipStream_t s);
 

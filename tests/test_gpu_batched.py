@@ -311,3 +311,30 @@ def test_grouped_narrow_kernel_forms(form, monkeypatch):
         _, sv_o, _ = orsvd.rsvd(a.astype(np.float64), omega.omega_f16(21, j, a.shape[1], k + s), k, 0)
         assert np.abs(host(sv) - sv_o).max() <= 1e-5 * sv_o[0], (form, j)
     c.close()
+
+
+@pytest.mark.parametrize("graph_sweeps", ["0", "2"])
+def test_batched_eager_jacobi_sweeps_match_graph(graph_sweeps, monkeypatch):
+    """Jacobi sweeps beyond the first graph's run eagerly while a problem is
+    open: with 0 or 2 sweeps in the graph (RPMI_BATCHED_GRAPH_SWEEPS) the
+    same sweeps run in the same order as with the default count, so S, U and
+    V^T are bit-identical, on the first call and on a replay.  Gaussian
+    inputs of widths 20 to 48 need more sweeps than either count."""
+    rng = np.random.default_rng(31)
+    shapes = [(300, 200), (260, 180), (150, 120)]
+    ks, ss = [40, 24, 12], [8, 8, 8]
+    announce(f"eager Jacobi sweeps after {graph_sweeps} captured: rsvd_batched {shapes}")
+    mats = [dev(rng.standard_normal(s).astype(np.float32)) for s in shapes]
+    c1 = rp().Context(0)
+    ref = rp().rsvd_batched(mats, ks, ss, 0, 9, "f16", ctx=c1)
+    monkeypatch.setenv("RPMI_BATCHED_GRAPH_SWEEPS", graph_sweeps)
+    c2 = rp().Context(0)
+    for _ in range(2):   # capture, then replay
+        out = rp().rsvd_batched(mats, ks, ss, 0, 9, "f16", ctx=c2)
+        for (u1, s1, v1), (u2, s2, v2) in zip(ref, out):
+            assert np.array_equal(host(s1), host(s2))
+            assert np.array_equal(host(u1), host(u2))
+            assert np.array_equal(host(v1), host(v2))
+    assert rp().status_string(rp().rp_get_device_status(clear=True, ctx=c2)) == "RP_OK"
+    for c in (c1, c2):
+        c.close()
