@@ -59,69 +59,65 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(
 }
 
 // ---------------------------------------------------------------- Cholesky
-// Factor the nb x nb diagonal block at (k, k) in place (lower), in LDS.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// The nb x nb diagonal block at (k, k), nb <= 64, factored in place by one
-// wave: lane i holds row i in registers; step j takes the pivot from lane j,
-// scales column j and updates the trailing rows with the column values of
-// lanes l > j read by v_readlane (no LDS, no barriers).
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* A, int64_t lda, int64_t k, int nb,
-                                                        unsigned int* status) {
-    const int i = threadIdx.x;
-    double tr[NB];
-#pragma unroll
-    for (int l = 0; l < NB; ++l) tr[l] = (i < nb && l < nb && l <= i) ? A[(k + i) * lda + k + l] : 0.0;
-    // (rows and columns past nb are zero and stay zero: their pivots are
-    // never taken, and the updates they receive are zero)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        double v = readlane_f64(tr[j], j);
-        if (j < nb && !(v > 0.0)) {                  // breakdown (or NaN): record, keep going
-            if (i == 0) atomicOr(status, kStatusNotSpd);
+// The nb x nb diagonal block at (k, k), nb <= NB, factored in place in LDS by
+// one workgroup, right-looking: step j takes the pivot, scales column j and
+// updates the trailing triangle, each wave whole rows of it (lane l column
+// j + 1 + l), so a step is a few instructions per lane between barriers.
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, int64_t lda, int64_t k, int nb,
+                                                         unsigned int* status) {
+    __shared__ double T[NB][NB + 1];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, l = e % nb;
+        T[i][l] = l <= i ? A[(k + i) * lda + k + l] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        double v = T[j][j];
+        if (!(v > 0.0)) {                            // breakdown (or NaN): record, keep going
+            if (tid == 0) atomicOr(status, kStatusNotSpd);
             v = fabs(v) > 0.0 ? fabs(v) : 1.0;
         }
-        const double d = j < nb ? sqrt(v) : 1.0;
-        tr[j] = i == j ? d : (i > j ? tr[j] / d : tr[j]);
-#pragma unroll
-        for (int l = j + 1; l < NB; ++l) {
-            const double llj = readlane_f64(tr[j], l);
-            tr[l] = i >= l ? tr[l] - tr[j] * llj : tr[l];
-        }
+        const double d = sqrt(v);
+        __syncthreads();                             // T[j][j] read by every thread before it changes
+        if (tid >= j && tid < nb) T[tid][j] = tid == j ? d : T[tid][j] / d;
+        __syncthreads();
+        const int l = j + 1 + tx;
+        const double llj = l < nb ? T[l][j] : 0.0;
+        for (int i = j + 1 + ty; i < nb; i += 4)
+            if (l <= i) T[i][l] = T[i][l] - T[i][j] * llj;
+        __syncthreads();
     }
-    if (i < nb) {
-#pragma unroll
-        for (int l = 0; l < NB; ++l)
-            if (l < nb) A[(k + i) * lda + k + l] = l <= i ? tr[l] : 0.0;
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, l = e % nb;
+        A[(k + i) * lda + k + l] = l <= i ? T[i][l] : 0.0;
     }
 }
 
-// Rows [k+nb, p) of block column k: X <- X L_kk^-T (row by row forward
-// substitution; one workgroup per 64 rows, L_kk in LDS).
+// Rows [k+nb, p) of block column k: X <- X L_kk^-T, one workgroup per 64
+// rows with L_kk and the rows in LDS.  Right-looking: step j divides column j
+// by L[j][j] (lane r: row r), then the four waves take the later columns in
+// turn (x_l -= x_j L[l][j]), so each x_l receives its terms in the order
+// l' = 0, 1, .. of the row-by-row substitution.
 __global__ __launch_bounds__(256) void trsm_panel_kernel(double* A, int64_t lda, int64_t k, int nb,
                                                          int64_t p) {
     __shared__ double L[NB][NB + 1];
     __shared__ double X[64][NB + 1];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int64_t r0 = k + nb + blockIdx.x * 64;
     const int rows = (int)(p - r0 < 64 ? p - r0 : 64);
     for (int e = tid; e < nb * nb; e += 256) L[e / nb][e % nb] = A[(k + e / nb) * lda + k + e % nb];
     for (int e = tid; e < rows * nb; e += 256) X[e / nb][e % nb] = A[(r0 + e / nb) * lda + k + e % nb];
     __syncthreads();
-    // x_j = (x_j - sum_{l<j} x_l L[j][l]) / L[j][j], for each row independently
-    if (tid < rows) {
-        for (int j = 0; j < nb; ++j) {
-            double s = X[tid][j];
-            for (int l = 0; l < j; ++l) s -= X[tid][l] * L[j][l];
-            X[tid][j] = s / L[j][j];
+    for (int j = 0; j < nb; ++j) {
+        if (tid < rows) X[tid][j] = X[tid][j] / L[j][j];
+        __syncthreads();
+        if (tx < rows) {
+            const double xj = X[tx][j];
+            for (int l = j + 1 + ty; l < nb; l += 4) X[tx][l] = X[tx][l] - xj * L[l][j];
         }
+        __syncthreads();
     }
-    __syncthreads();
     for (int e = tid; e < rows * nb; e += 256) A[(r0 + e / nb) * lda + k + e % nb] = X[e / nb][e % nb];
 }
 
@@ -965,7 +961,7 @@ hipError_t potrf_lower(double* A, int64_t lda, int64_t p, unsigned int* status, 
     if ((e = launch_zero_upper(A, lda, p, s)) != hipSuccess) return e;
     for (int64_t k = 0; k < p; k += NB) {
         const int nb = (int)(p - k < NB ? p - k : NB);
-        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, s, A, lda, k, nb, status);
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, A, lda, k, nb, status);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t below = p - k - nb;
         if (below <= 0) break;
