@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_group_kernel(const Chol
 // 16 rows are loaded before the products of the current ones.  Jobs come
 // longest contraction chunk first (the host orders the table), so that the
 // longest waves start first.
-__global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm_tn_f32_group_kernel(const TnJob* __restrict__ jobs,
                                                                 const int64_t* __restrict__ starts, int count) {
     typedef float f4 __attribute__((ext_vector_type(4)));
     const int64_t blk = blockIdx.x;
@@ -212,6 +212,10 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
             qv[u] = in ? load4(J.Q + k * J.ldq, j0, J.P) : f4{0.f, 0.f, 0.f, 0.f};
         }
     };
+    // 16 x 16 tiles wholly past N or P have no output: their products are
+    // skipped (the tests are uniform over the wave)
+    const int na = J.N - i0 >= 64 ? 4 : (int)((J.N - i0 + 15) / 16);
+    const int nbt = J.P - j0 >= 64 ? 4 : (int)((J.P - j0 + 15) / 16);
     f4 av[4], qv[4];
     load_step(kbeg, av, qv);
     for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
@@ -224,7 +228,8 @@ __global__ __launch_bounds__(256) void gemm_tn_f32_group_kernel(const TnJob* __r
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
+                    if (a < na && b < nbt)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][a], qv[u][b], acc[a][b], 0, 0, 0);
         if (more) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
